@@ -1,0 +1,161 @@
+/*
+ * fft2d.h -- C ABI of the MI355X (gfx950) complex 2D FFT library.
+ *
+ * The operation is the 2D discrete Fourier transform of FP32 complex data,
+ * computed as the paper computes it (Brown, Davies, Le Clair, "Exploring Fast
+ * Fourier Transforms on the Tenstorrent Wormhole", arXiv 2506.15437): radix-2
+ * Cooley-Tukey butterflies with precomputed twiddle factors on bit-reversal
+ * reordered data (Section 2.2, Listing 1, Fig. 2), applied as one FFT along
+ * every row followed by one FFT down every column (Section 5, Fig. 6).
+ *
+ * Definition (the paper does not write it out; this is the library's reading):
+ *   forward  X[k][l] = sum_{m<M} sum_{n<N} x[m][n] exp(-2 pi i (k m/M + l n/N))
+ *   inverse  x[m][n] = 1/(M N) sum_{k<M} sum_{l<N} X[k][l] exp(+2 pi i (k m/M + l n/N))
+ * Results are in natural order, same shape as the input.
+ *
+ * Data layout: complex64 = { float re; float im; } interleaved, 8 bytes per
+ * point. A uniform plan works on [batch][rows][cols] contiguous, cols fastest.
+ * All data pointers are DEVICE pointers owned by the caller and must be 8-byte
+ * aligned (16-byte alignment is recommended). Sizes must be powers of two in
+ * [1, 16384] per dimension.
+ *
+ * Streams: `stream` is a hipStream_t passed as void* (NULL = the default
+ * stream). Every exec/backward call only enqueues work on that stream; it never
+ * synchronises and never allocates, so it can be captured in a HIP graph.
+ *
+ * Errors: every function returns an fft2d_status and never throws. On failure
+ * nothing is enqueued, outputs are untouched, and fft2d_last_error() gives a
+ * thread-local detail string.
+ *
+ * Thread safety: a uniform plan is read-only during execution and may be used
+ * from several host threads and streams at once. A batched plan owns mutable
+ * device state (work counters, descriptor table): use it from one stream at a
+ * time.
+ */
+#ifndef FFT2D_H
+#define FFT2D_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Sign of the exponent: FORWARD is unscaled, INVERSE is scaled by 1/(M N). */
+#define FFT2D_FORWARD (-1)
+#define FFT2D_INVERSE (+1)
+
+/* Largest supported length along one dimension (2^14). */
+#define FFT2D_MAX_LEN 16384
+
+typedef enum fft2d_status {
+  FFT2D_OK = 0,
+  FFT2D_ERR_NULL_POINTER = 1,      /* a required pointer argument is NULL */
+  FFT2D_ERR_INVALID_SIZE = 2,      /* a size is not a power of two in [1, 16384], or a count is < 1 */
+  FFT2D_ERR_INVALID_DIRECTION = 3, /* direction is neither FFT2D_FORWARD nor FFT2D_INVERSE */
+  FFT2D_ERR_MISALIGNED = 4,        /* a data pointer is not 8-byte aligned */
+  FFT2D_ERR_WRONG_PLAN_KIND = 5,   /* uniform plan given to a batched call, or the reverse */
+  FFT2D_ERR_OUT_OF_MEMORY = 6,     /* plan creation could not allocate host or device memory */
+  FFT2D_ERR_HIP = 7,               /* a HIP runtime call failed; see fft2d_last_error() */
+  FFT2D_ERR_INVALID_PLAN = 8,      /* the handle is not a live plan (e.g. already destroyed) */
+  FFT2D_ERR_OVERLAP = 9            /* input and output partially overlap (exact aliasing is allowed) */
+} fft2d_status;
+
+/* Opaque plan handle, owned by the library until fft2d_destroy(). */
+typedef struct fft2d_plan_s* fft2d_plan_t;
+
+/*
+ * fft2d_plan -- create a plan for `batch` independent rows x cols transforms.
+ *   out    : receives the handle (set to NULL on failure).
+ *   batch  : number of grids, >= 1; grids are contiguous, rows*cols points apart.
+ *   rows   : M, power of two in [1, 16384] (rows = 1 gives a batch of 1D FFTs).
+ *   cols   : N, power of two in [1, 16384], the contiguous dimension.
+ * Builds the FP32 twiddle tables (each entry computed in FP64 from its own
+ * angle and rounded once; the paper precomputes its twiddles at start-up,
+ * Section 4) in device memory on the current HIP device, and chooses the radix
+ * schedule and tile shape for each pass. Must be called with a GPU present.
+ */
+fft2d_status fft2d_plan(fft2d_plan_t* out, int64_t batch, int64_t rows, int64_t cols);
+
+/*
+ * fft2d_plan_batched -- plan `count` independent transforms of different shapes
+ * (rows[i] x cols[i], powers of two in [1, 16384]), executed by
+ * fft2d_exec_batched in one persistent kernel launch replayed from a HIP graph.
+ * rows and cols are host arrays of `count` entries, read during the call only.
+ * Radix schedule, tile shape and persistent grid size come from the library's
+ * autotuner (a cached choice per shape class when one exists).
+ */
+fft2d_status fft2d_plan_batched(fft2d_plan_t* out, int64_t count, const int64_t* rows, const int64_t* cols);
+
+/*
+ * fft2d_exec -- transform every grid of a uniform plan.
+ *   in, out   : device pointers to batch*rows*cols complex64; in == out (in
+ *               place) is allowed, partial overlap is rejected.
+ *   direction : FFT2D_FORWARD or FFT2D_INVERSE (definition above).
+ *   stream    : hipStream_t as void*.
+ * Work: one row pass and one column pass (Section 5), each reading and writing
+ * every point once.
+ */
+fft2d_status fft2d_exec(fft2d_plan_t plan, const void* in, void* out, int direction, void* stream);
+
+/*
+ * fft2d_exec_batched -- transform every grid of a batched plan.
+ *   in, out : HOST arrays of `count` device pointers (grid i has the shape given
+ *             at plan time); in[i] == out[i] is allowed. The arrays are read
+ *             during the call only. When the pointer set differs from the
+ *             previous call's, the device descriptor table is refreshed by a
+ *             stream-ordered copy before the launch.
+ *   direction, stream : as for fft2d_exec.
+ */
+fft2d_status fft2d_exec_batched(fft2d_plan_t plan, const void* const* in, void* const* out, int direction,
+                                void* stream);
+
+/*
+ * fft2d_backward -- vector-Jacobian product (adjoint) of fft2d_exec, for
+ * reverse-mode differentiation. With the convention grad = dL/dRe + i dL/dIm:
+ *   forward_direction == FFT2D_FORWARD : grad_in = F^H grad_out, the unscaled
+ *                                        opposite-sign transform;
+ *   forward_direction == FFT2D_INVERSE : grad_in = (1/(M N)) F grad_out.
+ * grad_out, grad_in : device pointers shaped like the plan's data; may alias.
+ * This is not the inverse transform (that is fft2d_exec with FFT2D_INVERSE).
+ */
+fft2d_status fft2d_backward(fft2d_plan_t plan, const void* grad_out, void* grad_in, int forward_direction,
+                            void* stream);
+
+/*
+ * fft2d_exec_pass -- enqueue only one of the two passes of fft2d_exec, for
+ * profiling and per-pass timing: pass 0 is the row pass (length-cols FFT along
+ * every row), pass 1 the column pass (length-rows FFT down every column).
+ * fft2d_exec(in, out) is exactly pass 0 (in -> out) followed by pass 1
+ * (out -> out). The inverse's 1/(M N) scale is applied by the column pass (by
+ * the row pass when rows == 1). Returns FFT2D_ERR_INVALID_SIZE if the plan has
+ * no such pass (that dimension has length 1) and FFT2D_ERR_INVALID_DIRECTION
+ * for a pass index other than 0 or 1. Uniform plans only.
+ */
+fft2d_status fft2d_exec_pass(fft2d_plan_t plan, const void* in, void* out, int direction, int pass, void* stream);
+
+/* fft2d_destroy -- free a plan and its device memory. NULL is a no-op. Waits for
+ * no stream: the caller must make sure no enqueued work still uses the plan. */
+fft2d_status fft2d_destroy(fft2d_plan_t plan);
+
+/* Static English text for a status code. */
+const char* fft2d_status_string(fft2d_status status);
+
+/* Thread-local detail of the last failure on this host thread ("" if none). */
+const char* fft2d_last_error(void);
+
+/*
+ * fft2d_plan_describe -- write a one-line, NUL-terminated description of the
+ * plan's chosen kernels (radix schedules, tile shapes, grid sizes) into buf
+ * (at most buflen bytes, truncated if needed).
+ */
+fft2d_status fft2d_plan_describe(fft2d_plan_t plan, char* buf, int64_t buflen);
+
+/* Library version as MAJOR*10000 + MINOR*100 + PATCH. */
+int fft2d_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FFT2D_H */

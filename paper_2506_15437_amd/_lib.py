@@ -1,0 +1,144 @@
+"""ctypes binding of ``libfft2d.so``: the C ABI under the same names.
+
+Only argument marshalling lives here; every step of the transform runs in the
+library's HIP kernels. Pointers are passed as Python ints (device addresses),
+streams as ints (hipStream_t values, 0 = default stream). Every function
+raises ``Fft2dError`` when the library returns a non-zero status.
+
+The library is built in-tree by ``paper_2506_15437_amd.build``; if it is
+missing this module raises at import time instead of falling back to
+anything else.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libfft2d.so")
+
+FORWARD = -1
+INVERSE = +1
+MAX_LEN = 16384
+
+STATUS_NAMES = {
+    0: "FFT2D_OK",
+    1: "FFT2D_ERR_NULL_POINTER",
+    2: "FFT2D_ERR_INVALID_SIZE",
+    3: "FFT2D_ERR_INVALID_DIRECTION",
+    4: "FFT2D_ERR_MISALIGNED",
+    5: "FFT2D_ERR_WRONG_PLAN_KIND",
+    6: "FFT2D_ERR_OUT_OF_MEMORY",
+    7: "FFT2D_ERR_HIP",
+    8: "FFT2D_ERR_INVALID_PLAN",
+    9: "FFT2D_ERR_OVERLAP",
+}
+
+# Every symbol the public header declares.
+EXPORTS = ("fft2d_plan", "fft2d_plan_batched", "fft2d_exec", "fft2d_exec_pass", "fft2d_exec_batched",
+           "fft2d_backward", "fft2d_destroy", "fft2d_status_string", "fft2d_last_error", "fft2d_plan_describe", "fft2d_version")
+
+
+class Fft2dError(RuntimeError):
+    def __init__(self, status, where, detail):
+        self.status = status
+        self.name = STATUS_NAMES.get(status, "status %d" % status)
+        super().__init__("%s: %s (%s)%s" % (where, self.name, status_string(status), (": " + detail) if detail else ""))
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libfft2d.so is not built (expected at %s); run `python -m paper_2506_15437_amd.build`"
+                          % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    vp = ctypes.c_void_p
+    i64 = ctypes.c_int64
+    ci = ctypes.c_int
+    pp = ctypes.POINTER(vp)
+    lib.fft2d_plan.argtypes = [pp, i64, i64, i64]
+    lib.fft2d_plan_batched.argtypes = [pp, i64, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    lib.fft2d_exec.argtypes = [vp, vp, vp, ci, vp]
+    lib.fft2d_exec_pass.argtypes = [vp, vp, vp, ci, ci, vp]
+    lib.fft2d_exec_batched.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ci, vp]
+    lib.fft2d_backward.argtypes = [vp, vp, vp, ci, vp]
+    lib.fft2d_destroy.argtypes = [vp]
+    lib.fft2d_status_string.argtypes = [ci]
+    lib.fft2d_status_string.restype = ctypes.c_char_p
+    lib.fft2d_last_error.argtypes = []
+    lib.fft2d_last_error.restype = ctypes.c_char_p
+    lib.fft2d_plan_describe.argtypes = [vp, ctypes.c_char_p, i64]
+    lib.fft2d_version.argtypes = []
+    lib.fft2d_version.restype = ci
+    for f in ("fft2d_plan", "fft2d_plan_batched", "fft2d_exec", "fft2d_exec_pass", "fft2d_exec_batched", "fft2d_backward",
+              "fft2d_destroy", "fft2d_plan_describe"):
+        getattr(lib, f).restype = ci
+    return lib
+
+
+lib = _load()
+
+
+def status_string(status: int) -> str:
+    return lib.fft2d_status_string(int(status)).decode()
+
+
+def last_error() -> str:
+    return lib.fft2d_last_error().decode()
+
+
+def _check(status, where):
+    if status != 0:
+        raise Fft2dError(status, where, last_error())
+
+
+def version() -> int:
+    return int(lib.fft2d_version())
+
+
+def fft2d_plan(batch: int, rows: int, cols: int) -> int:
+    """Create a uniform plan; returns the opaque handle as an int."""
+    h = ctypes.c_void_p()
+    _check(lib.fft2d_plan(ctypes.byref(h), int(batch), int(rows), int(cols)), "fft2d_plan")
+    return int(h.value)
+
+
+def fft2d_plan_batched(rows, cols) -> int:
+    """Create a batched plan for shapes rows[i] x cols[i]; returns the handle."""
+    n = len(rows)
+    if len(cols) != n:
+        raise ValueError("rows and cols must have the same length")
+    ra = (ctypes.c_int64 * max(n, 1))(*[int(r) for r in rows])
+    ca = (ctypes.c_int64 * max(n, 1))(*[int(c) for c in cols])
+    h = ctypes.c_void_p()
+    _check(lib.fft2d_plan_batched(ctypes.byref(h), n, ra, ca), "fft2d_plan_batched")
+    return int(h.value)
+
+
+def fft2d_exec(plan: int, in_ptr: int, out_ptr: int, direction: int, stream: int = 0) -> None:
+    _check(lib.fft2d_exec(plan, in_ptr, out_ptr, int(direction), stream), "fft2d_exec")
+
+
+def fft2d_exec_pass(plan: int, in_ptr: int, out_ptr: int, direction: int, pass_index: int, stream: int = 0) -> None:
+    _check(lib.fft2d_exec_pass(plan, in_ptr, out_ptr, int(direction), int(pass_index), stream), "fft2d_exec_pass")
+
+
+def fft2d_exec_batched(plan: int, in_ptrs, out_ptrs, direction: int, stream: int = 0) -> None:
+    n = len(in_ptrs)
+    ia = (ctypes.c_void_p * max(n, 1))(*[int(p) for p in in_ptrs])
+    oa = (ctypes.c_void_p * max(n, 1))(*[int(p) for p in out_ptrs])
+    _check(lib.fft2d_exec_batched(plan, ia, oa, int(direction), stream), "fft2d_exec_batched")
+
+
+def fft2d_backward(plan: int, grad_out_ptr: int, grad_in_ptr: int, forward_direction: int, stream: int = 0) -> None:
+    _check(lib.fft2d_backward(plan, grad_out_ptr, grad_in_ptr, int(forward_direction), stream), "fft2d_backward")
+
+
+def fft2d_destroy(plan: int) -> None:
+    _check(lib.fft2d_destroy(plan), "fft2d_destroy")
+
+
+def fft2d_plan_describe(plan: int) -> str:
+    buf = ctypes.create_string_buffer(4096)
+    _check(lib.fft2d_plan_describe(plan, buf, len(buf)), "fft2d_plan_describe")
+    return buf.value.decode()

@@ -1,0 +1,355 @@
+// C ABI runtime of the 2D FFT library: plans, FP64-derived twiddle tables,
+// argument validation, and the row-pass / column-pass launch sequence.
+//
+// A 2D transform is one FFT along every row followed by one FFT down every
+// column (the paper's Section 5 / Fig. 6 scheme: row FFTs, transposition,
+// row FFTs; here the transposition is the column pass's strided tile access,
+// so the result stays in natural [k][l] order). Each pass is one kernel launch
+// that reads and writes every point once.
+#include "../../include/fft2d.h"
+#include "fft_batched.h"
+#include "fft_internal.h"
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <unordered_set>
+#include <vector>
+
+using namespace fft2d;
+
+namespace {
+
+constexpr int kVersion = 100;  // 0.1.0
+
+thread_local std::string g_last_error;
+std::mutex g_plans_mu;
+std::unordered_set<const void*> g_live_plans;
+
+fft2d_status fail(fft2d_status st, const std::string& detail) {
+  g_last_error = detail;
+  return st;
+}
+
+fft2d_status hip_fail(hipError_t e, const char* what) {
+  return fail(FFT2D_ERR_HIP, std::string(what) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")");
+}
+
+bool pow2_in_range(int64_t n) { return n >= 1 && n <= FFT2D_MAX_LEN && (n & (n - 1)) == 0; }
+
+enum PlanKind { kUniform = 1, kBatched = 2 };
+
+}  // namespace
+
+struct fft2d_plan_s {
+  int kind = kUniform;
+  int device = 0;
+  int64_t batch = 0, rows = 0, cols = 0;
+  const PassKernel* row_k = nullptr;  // length-cols FFT along rows (null if cols == 1)
+  const PassKernel* col_k = nullptr;  // length-rows FFT down columns (null if rows == 1)
+  float2* tw_row = nullptr;
+  float2* tw_col = nullptr;
+  BatchedPlan* batched = nullptr;
+};
+
+namespace fft2d {
+
+void fill_twiddles(const PassKernel& k, float2* tab) {
+  // Pass p >= 1, radix R, Ns = product of earlier radices: entry (r, k) is
+  // exp(-2 pi i k r / (Ns R)) for r in [1, R), k in [0, Ns). The exponent
+  // k r < Ns R is reduced exactly; every value comes from its own FP64 cos/sin
+  // and is rounded once to FP32 (no recurrences).
+  size_t o = 0;
+  int64_t ns = 1;
+  for (int p = 0; p < k.npass; ++p) {
+    const int R = k.radix[p];
+    if (p > 0) {
+      const int64_t span = ns * R;
+      for (int r = 1; r < R; ++r) {
+        for (int64_t kk = 0; kk < ns; ++kk) {
+          const double a = 2.0 * M_PI * (double)(kk * r) / (double)span;
+          tab[o++] = make_float2((float)std::cos(a), (float)(-std::sin(a)));
+        }
+      }
+    }
+    ns *= R;
+  }
+}
+
+hipError_t upload_twiddles(const PassKernel& k, float2** dev) {
+  *dev = nullptr;
+  const size_t n = twiddle_count(k);
+  if (n == 0) return hipSuccess;
+  std::vector<float2> host(n);
+  fill_twiddles(k, host.data());
+  hipError_t e = hipMalloc((void**)dev, n * sizeof(float2));
+  if (e != hipSuccess) {
+    *dev = nullptr;
+    return e;
+  }
+  e = hipMemcpy(*dev, host.data(), n * sizeof(float2), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(*dev);
+    *dev = nullptr;
+  }
+  return e;
+}
+
+// Enqueue the row pass then the column pass of `batch` grids of rows x cols
+// (only_pass = 0 or 1 restricts it to one of them).
+fft2d_status run_uniform(const fft2d_plan_s* p, const float2* in, float2* out, int sign, float scale,
+                         hipStream_t s, int only_pass = -1) {
+  const int64_t npts = p->batch * p->rows * p->cols;
+  hipError_t e;
+  if (!p->row_k && !p->col_k) {
+    e = launch_scale_copy(in, out, npts, scale, s);
+    return e == hipSuccess ? FFT2D_OK : hip_fail(e, "scale copy launch");
+  }
+  const float2* src = in;
+  if (p->row_k && only_pass != 1) {
+    PassArgs a{};
+    a.in = src;
+    a.out = out;
+    a.tw = p->tw_row;
+    a.nvec = p->batch * p->rows;
+    a.ncols = p->cols;
+    a.scale = p->col_k ? 1.0f : scale;
+    a.nblocks = pass_blocks(*p->row_k, a.nvec);
+    e = p->row_k->launch(a, sign, s);
+    if (e != hipSuccess) return hip_fail(e, "row pass launch");
+    src = out;
+  }
+  if (p->col_k && only_pass != 0) {
+    PassArgs a{};
+    a.in = src;
+    a.out = out;
+    a.tw = p->tw_col;
+    a.nvec = p->batch * p->cols;
+    a.ncols = p->cols;
+    a.scale = scale;
+    a.nblocks = pass_blocks(*p->col_k, a.nvec);
+    e = p->col_k->launch(a, sign, s);
+    if (e != hipSuccess) return hip_fail(e, "column pass launch");
+  }
+  return FFT2D_OK;
+}
+
+}  // namespace fft2d
+
+namespace {
+
+bool is_live(const void* p) {
+  std::lock_guard<std::mutex> g(g_plans_mu);
+  return g_live_plans.count(p) != 0;
+}
+
+void free_plan(fft2d_plan_s* p) {
+  if (!p) return;
+  if (p->tw_row) (void)hipFree(p->tw_row);
+  if (p->tw_col) (void)hipFree(p->tw_col);
+  if (p->batched) destroy_batched(p->batched);
+  delete p;
+}
+
+fft2d_status check_data_ptrs(const void* in, const void* out, int64_t bytes) {
+  if (!in || !out) return fail(FFT2D_ERR_NULL_POINTER, "input or output pointer is NULL");
+  if ((reinterpret_cast<uintptr_t>(in) & 7) || (reinterpret_cast<uintptr_t>(out) & 7))
+    return fail(FFT2D_ERR_MISALIGNED, "data pointers must be 8-byte aligned (complex64)");
+  const uintptr_t a = reinterpret_cast<uintptr_t>(in), b = reinterpret_cast<uintptr_t>(out);
+  if (a != b && a < b + (uintptr_t)bytes && b < a + (uintptr_t)bytes)
+    return fail(FFT2D_ERR_OVERLAP, "input and output overlap without being identical");
+  return FFT2D_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fft2d_status fft2d_plan(fft2d_plan_t* out, int64_t batch, int64_t rows, int64_t cols) {
+  if (!out) return fail(FFT2D_ERR_NULL_POINTER, "plan output pointer is NULL");
+  *out = nullptr;
+  if (batch < 1) return fail(FFT2D_ERR_INVALID_SIZE, "batch must be >= 1");
+  if (!pow2_in_range(rows) || !pow2_in_range(cols))
+    return fail(FFT2D_ERR_INVALID_SIZE, "rows and cols must be powers of two in [1, 16384], got " +
+                                            std::to_string(rows) + "x" + std::to_string(cols));
+  if (batch > (int64_t(1) << 40) / (rows * cols)) return fail(FFT2D_ERR_INVALID_SIZE, "batch*rows*cols too large");
+  fft2d_plan_s* p = new (std::nothrow) fft2d_plan_s();
+  if (!p) return fail(FFT2D_ERR_OUT_OF_MEMORY, "host allocation failed");
+  p->kind = kUniform;
+  p->batch = batch;
+  p->rows = rows;
+  p->cols = cols;
+  hipError_t e = hipGetDevice(&p->device);
+  if (e != hipSuccess) {
+    delete p;
+    return hip_fail(e, "hipGetDevice");
+  }
+  if (cols > 1) p->row_k = find_pass_kernel((int)cols, false);
+  if (rows > 1) p->col_k = find_pass_kernel((int)rows, true);
+  if ((cols > 1 && !p->row_k) || (rows > 1 && !p->col_k)) {
+    delete p;
+    return fail(FFT2D_ERR_INVALID_SIZE, "no kernel for this length");
+  }
+  if (p->row_k && (e = upload_twiddles(*p->row_k, &p->tw_row)) != hipSuccess) {
+    free_plan(p);
+    return e == hipErrorOutOfMemory ? fail(FFT2D_ERR_OUT_OF_MEMORY, "twiddle table") : hip_fail(e, "twiddle upload");
+  }
+  if (p->col_k && (e = upload_twiddles(*p->col_k, &p->tw_col)) != hipSuccess) {
+    free_plan(p);
+    return e == hipErrorOutOfMemory ? fail(FFT2D_ERR_OUT_OF_MEMORY, "twiddle table") : hip_fail(e, "twiddle upload");
+  }
+  {
+    std::lock_guard<std::mutex> g(g_plans_mu);
+    g_live_plans.insert(p);
+  }
+  *out = p;
+  return FFT2D_OK;
+}
+
+fft2d_status fft2d_plan_batched(fft2d_plan_t* out, int64_t count, const int64_t* rows, const int64_t* cols) {
+  if (!out) return fail(FFT2D_ERR_NULL_POINTER, "plan output pointer is NULL");
+  *out = nullptr;
+  if (!rows || !cols) return fail(FFT2D_ERR_NULL_POINTER, "rows/cols arrays are NULL");
+  if (count < 1 || count > (int64_t(1) << 24)) return fail(FFT2D_ERR_INVALID_SIZE, "count must be in [1, 2^24]");
+  for (int64_t i = 0; i < count; ++i)
+    if (!pow2_in_range(rows[i]) || !pow2_in_range(cols[i]))
+      return fail(FFT2D_ERR_INVALID_SIZE, "shape " + std::to_string(i) + " is not a power of two in [1, 16384]");
+  fft2d_plan_s* p = new (std::nothrow) fft2d_plan_s();
+  if (!p) return fail(FFT2D_ERR_OUT_OF_MEMORY, "host allocation failed");
+  p->kind = kBatched;
+  p->batch = count;
+  hipError_t e = hipGetDevice(&p->device);
+  if (e != hipSuccess) {
+    delete p;
+    return hip_fail(e, "hipGetDevice");
+  }
+  std::string err;
+  fft2d_status st = create_batched(count, rows, cols, &p->batched, &err);
+  if (st != FFT2D_OK) {
+    delete p;
+    return fail(st, err);
+  }
+  {
+    std::lock_guard<std::mutex> g(g_plans_mu);
+    g_live_plans.insert(p);
+  }
+  *out = p;
+  return FFT2D_OK;
+}
+
+fft2d_status fft2d_exec(fft2d_plan_t plan, const void* in, void* out, int direction, void* stream) {
+  if (!plan) return fail(FFT2D_ERR_NULL_POINTER, "plan is NULL");
+  if (!is_live(plan)) return fail(FFT2D_ERR_INVALID_PLAN, "plan handle is not live");
+  if (plan->kind != kUniform) return fail(FFT2D_ERR_WRONG_PLAN_KIND, "batched plan passed to fft2d_exec");
+  if (direction != FFT2D_FORWARD && direction != FFT2D_INVERSE)
+    return fail(FFT2D_ERR_INVALID_DIRECTION, "direction must be FFT2D_FORWARD (-1) or FFT2D_INVERSE (+1)");
+  const int64_t bytes = plan->batch * plan->rows * plan->cols * 8;
+  fft2d_status st = check_data_ptrs(in, out, bytes);
+  if (st != FFT2D_OK) return st;
+  const float scale = direction == FFT2D_INVERSE ? (float)(1.0 / (double)(plan->rows * plan->cols)) : 1.0f;
+  return run_uniform(plan, (const float2*)in, (float2*)out, direction, scale, (hipStream_t)stream);
+}
+
+fft2d_status fft2d_backward(fft2d_plan_t plan, const void* grad_out, void* grad_in, int forward_direction,
+                            void* stream) {
+  if (!plan) return fail(FFT2D_ERR_NULL_POINTER, "plan is NULL");
+  if (!is_live(plan)) return fail(FFT2D_ERR_INVALID_PLAN, "plan handle is not live");
+  if (plan->kind != kUniform) return fail(FFT2D_ERR_WRONG_PLAN_KIND, "batched plan passed to fft2d_backward");
+  if (forward_direction != FFT2D_FORWARD && forward_direction != FFT2D_INVERSE)
+    return fail(FFT2D_ERR_INVALID_DIRECTION, "direction must be FFT2D_FORWARD (-1) or FFT2D_INVERSE (+1)");
+  const int64_t bytes = plan->batch * plan->rows * plan->cols * 8;
+  fft2d_status st = check_data_ptrs(grad_out, grad_in, bytes);
+  if (st != FFT2D_OK) return st;
+  // Adjoint of y = F x (sign -1, unscaled) is F^H: sign +1, unscaled.
+  // Adjoint of y = (1/MN) F^H x is (1/MN) F: sign -1, scaled.
+  const int sign = -forward_direction;
+  const float scale = forward_direction == FFT2D_INVERSE ? (float)(1.0 / (double)(plan->rows * plan->cols)) : 1.0f;
+  return run_uniform(plan, (const float2*)grad_out, (float2*)grad_in, sign, scale, (hipStream_t)stream);
+}
+
+fft2d_status fft2d_exec_pass(fft2d_plan_t plan, const void* in, void* out, int direction, int pass, void* stream) {
+  if (!plan) return fail(FFT2D_ERR_NULL_POINTER, "plan is NULL");
+  if (!is_live(plan)) return fail(FFT2D_ERR_INVALID_PLAN, "plan handle is not live");
+  if (plan->kind != kUniform) return fail(FFT2D_ERR_WRONG_PLAN_KIND, "batched plan passed to fft2d_exec_pass");
+  if (direction != FFT2D_FORWARD && direction != FFT2D_INVERSE)
+    return fail(FFT2D_ERR_INVALID_DIRECTION, "direction must be FFT2D_FORWARD (-1) or FFT2D_INVERSE (+1)");
+  if (pass != 0 && pass != 1) return fail(FFT2D_ERR_INVALID_DIRECTION, "pass must be 0 (rows) or 1 (columns)");
+  if ((pass == 0 && !plan->row_k) || (pass == 1 && !plan->col_k))
+    return fail(FFT2D_ERR_INVALID_SIZE, "the plan has no such pass (that dimension has length 1)");
+  const int64_t bytes = plan->batch * plan->rows * plan->cols * 8;
+  fft2d_status st = check_data_ptrs(in, out, bytes);
+  if (st != FFT2D_OK) return st;
+  const float scale = direction == FFT2D_INVERSE ? (float)(1.0 / (double)(plan->rows * plan->cols)) : 1.0f;
+  return run_uniform(plan, (const float2*)in, (float2*)out, direction, scale, (hipStream_t)stream, pass);
+}
+
+fft2d_status fft2d_exec_batched(fft2d_plan_t plan, const void* const* in, void* const* out, int direction,
+                                void* stream) {
+  if (!plan) return fail(FFT2D_ERR_NULL_POINTER, "plan is NULL");
+  if (!is_live(plan)) return fail(FFT2D_ERR_INVALID_PLAN, "plan handle is not live");
+  if (plan->kind != kBatched) return fail(FFT2D_ERR_WRONG_PLAN_KIND, "uniform plan passed to fft2d_exec_batched");
+  if (direction != FFT2D_FORWARD && direction != FFT2D_INVERSE)
+    return fail(FFT2D_ERR_INVALID_DIRECTION, "direction must be FFT2D_FORWARD (-1) or FFT2D_INVERSE (+1)");
+  if (!in || !out) return fail(FFT2D_ERR_NULL_POINTER, "pointer arrays are NULL");
+  std::string err;
+  fft2d_status st = exec_batched(plan->batched, in, out, direction, (hipStream_t)stream, &err);
+  return st == FFT2D_OK ? st : fail(st, err);
+}
+
+fft2d_status fft2d_destroy(fft2d_plan_t plan) {
+  if (!plan) return FFT2D_OK;
+  {
+    std::lock_guard<std::mutex> g(g_plans_mu);
+    if (!g_live_plans.erase(plan)) return fail(FFT2D_ERR_INVALID_PLAN, "plan handle is not live");
+  }
+  free_plan(plan);
+  return FFT2D_OK;
+}
+
+const char* fft2d_status_string(fft2d_status st) {
+  switch (st) {
+    case FFT2D_OK: return "success";
+    case FFT2D_ERR_NULL_POINTER: return "null pointer";
+    case FFT2D_ERR_INVALID_SIZE: return "invalid size";
+    case FFT2D_ERR_INVALID_DIRECTION: return "invalid direction";
+    case FFT2D_ERR_MISALIGNED: return "misaligned pointer";
+    case FFT2D_ERR_WRONG_PLAN_KIND: return "wrong plan kind";
+    case FFT2D_ERR_OUT_OF_MEMORY: return "out of memory";
+    case FFT2D_ERR_HIP: return "HIP runtime error";
+    case FFT2D_ERR_INVALID_PLAN: return "invalid plan";
+    case FFT2D_ERR_OVERLAP: return "overlapping buffers";
+  }
+  return "unknown status";
+}
+
+const char* fft2d_last_error(void) { return g_last_error.c_str(); }
+
+fft2d_status fft2d_plan_describe(fft2d_plan_t plan, char* buf, int64_t buflen) {
+  if (!plan || !buf) return fail(FFT2D_ERR_NULL_POINTER, "plan or buffer is NULL");
+  if (buflen < 1) return fail(FFT2D_ERR_INVALID_SIZE, "buffer length must be >= 1");
+  if (!is_live(plan)) return fail(FFT2D_ERR_INVALID_PLAN, "plan handle is not live");
+  std::string d;
+  auto desc = [](const PassKernel* k) {
+    if (!k) return std::string("none");
+    std::string s = "L=" + std::to_string(k->L) + " radix=";
+    for (int i = 0; i < k->npass; ++i) s += (i ? "x" : "") + std::to_string(k->radix[i]);
+    s += " E=" + std::to_string(k->E) + " C=" + std::to_string(k->C) + " Q=" + std::to_string(k->Q) +
+         " threads=" + std::to_string(k->threads) + " lds=" + std::to_string(k->lds_bytes);
+    return s;
+  };
+  if (plan->kind == kUniform) {
+    d = "uniform batch=" + std::to_string(plan->batch) + " " + std::to_string(plan->rows) + "x" +
+        std::to_string(plan->cols) + " row[" + desc(plan->row_k) + "] col[" + desc(plan->col_k) + "]";
+  } else {
+    d = describe_batched(plan->batched);
+  }
+  std::snprintf(buf, (size_t)buflen, "%s", d.c_str());
+  return FFT2D_OK;
+}
+
+int fft2d_version(void) { return kVersion; }
+
+}  // extern "C"

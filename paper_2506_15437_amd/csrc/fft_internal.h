@@ -1,0 +1,57 @@
+// Internal interface between the C ABI runtime (fft2d.cpp) and the HIP kernels
+// (fft_kernels.hip). Not installed; not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace fft2d {
+
+constexpr int kMaxPasses = 6;
+
+// Arguments of one pass launch. A pass applies a length-L FFT to `nvec`
+// vectors. Row mode: vector v is the L contiguous points starting at v*L.
+// Column mode: vector v = g*ncols + col is column `col` of grid g, its element
+// e at g*L*ncols + e*ncols + col (stride ncols points).
+struct PassArgs {
+  const float2* in;
+  float2* out;
+  const float2* tw;   // inter-pass twiddle table of this pass kernel's schedule
+  int64_t nvec;       // number of vectors
+  int64_t ncols;      // column mode: points per row (N); unused in row mode
+  float scale;        // multiplies every output point
+  int nblocks;        // grid size (for the XCD-aware block remap)
+};
+
+// One compiled pass kernel: a length-L FFT with a fixed radix schedule,
+// E points per thread, C vectors per workgroup, exchanged through LDS in Q
+// rounds. `launch` enqueues it with the given exponent sign (-1 or +1).
+struct PassKernel {
+  int L, E, T, C, Q, threads;
+  int colmode;
+  int npass;
+  int radix[kMaxPasses];
+  size_t lds_bytes;
+  hipError_t (*launch)(const PassArgs&, int dir, hipStream_t);
+};
+
+// Default kernel for a length L in [2, 16384] (power of two); nullptr otherwise.
+const PassKernel* find_pass_kernel(int L, bool colmode);
+// All compiled variants for a length (for the autotuner); returns the count.
+int list_pass_kernels(int L, bool colmode, const PassKernel** out, int cap);
+
+// Grid size for a pass over nvec vectors.
+inline int pass_blocks(const PassKernel& k, int64_t nvec) { return (int)((nvec + k.C - 1) / k.C); }
+
+// Number of twiddle entries of a schedule and the table contents: for pass
+// p >= 1 with radix R and Ns = R_0 * ... * R_{p-1}, entry (r, k), r in
+// [1, R), k in [0, Ns), holds exp(-2 pi i k r / (Ns R)) computed in FP64 and
+// rounded once to FP32. Layout: passes in order, within a pass r-major.
+size_t twiddle_count(const PassKernel& k);
+void fill_twiddles(const PassKernel& k, float2* host_table);
+
+// Scaled copy for 1x1 grids (and the trivial dimension): out[i] = in[i]*scale.
+hipError_t launch_scale_copy(const float2* in, float2* out, int64_t n, float scale, hipStream_t s);
+
+}  // namespace fft2d

@@ -1,0 +1,117 @@
+"""CPU-only checks of the C ABI: the library loads, exports every declared
+symbol, and rejects bad arguments before touching the GPU."""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fft2d.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fft2d_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2506_15437_amd import _lib
+    return _lib
+
+
+def test_header_declares_the_entry_points():
+    names = _declared_functions()
+    for required in ("fft2d_plan", "fft2d_exec", "fft2d_exec_batched", "fft2d_backward"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(L):
+    names = _declared_functions()
+    assert sorted(L.EXPORTS) == names
+    raw = ctypes.CDLL(L.LIB_PATH)
+    for n in names:
+        assert hasattr(raw, n), n
+
+
+def test_status_strings_and_version(L):
+    assert L.status_string(0) == "success"
+    for code in range(1, 10):
+        s = L.status_string(code)
+        assert s and s != "unknown status"
+    assert L.status_string(99) == "unknown status"
+    assert L.version() >= 100
+
+
+@pytest.mark.parametrize("shape", [(1, 0, 8), (1, 8, 0), (1, 3, 8), (1, 8, 12), (1, 32768, 2), (1, 2, 32768),
+                                   (0, 8, 8), (-1, 8, 8), (1, -4, 8)])
+def test_plan_rejects_bad_sizes(L, shape):
+    with pytest.raises(L.Fft2dError) as e:
+        L.fft2d_plan(*shape)
+    assert e.value.status == 2
+
+
+def test_plan_rejects_null_out(L):
+    st = L.lib.fft2d_plan(None, 1, 8, 8)
+    assert st == 1
+
+
+def test_batched_plan_validation(L):
+    with pytest.raises(L.Fft2dError) as e:
+        L.fft2d_plan_batched([64, 48], [64, 64])
+    assert e.value.status == 2
+    with pytest.raises(L.Fft2dError) as e:
+        L.fft2d_plan_batched([], [])
+    assert e.value.status == 2
+    assert L.lib.fft2d_plan_batched(None, 1, None, None) == 1
+
+
+def test_exec_rejects_null_and_dead_plans(L):
+    assert L.lib.fft2d_exec(None, 8, 8, -1, None) == 1
+    assert L.lib.fft2d_backward(None, 8, 8, -1, None) == 1
+    # A handle that was never created is not live: rejected without being dereferenced.
+    bogus = ctypes.c_void_p(0x1000)
+    assert L.lib.fft2d_exec(bogus, 8, 8, -1, None) == 8
+    assert "not live" in L.last_error()
+    assert L.lib.fft2d_exec_batched(bogus, None, None, -1, None) == 8
+    assert L.lib.fft2d_destroy(bogus) == 8
+    assert L.lib.fft2d_destroy(None) == 0
+    buf = ctypes.create_string_buffer(16)
+    assert L.lib.fft2d_plan_describe(bogus, buf, 16) == 8
+
+
+def test_last_error_is_thread_local(L):
+    import threading
+    with pytest.raises(L.Fft2dError):
+        L.fft2d_plan(1, 3, 3)
+    main_msg = L.last_error()
+    seen = []
+
+    def other():
+        seen.append(L.last_error())
+
+    th = threading.Thread(target=other)
+    th.start()
+    th.join()
+    assert main_msg and seen == [""]
+
+
+def test_product_package_does_not_import_the_oracle():
+    import subprocess
+    import sys
+    code = ("import sys; import paper_2506_15437_amd; "
+            "bad = [m for m in sys.modules if m == 'oracle' or m.startswith('oracle.')]; "
+            "print(bad); sys.exit(1 if bad else 0)")
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True)
+    assert r.returncode == 0, r.stdout + r.stderr
+    for dirpath, _, files in os.walk(os.path.join(ROOT, "paper_2506_15437_amd")):
+        for f in files:
+            if f.endswith((".py", ".cpp", ".hip", ".h")):
+                src = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in src and "from oracle" not in src, f
+                assert "fft_oracle" not in src, f

@@ -1,0 +1,143 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Every comparison is relative L2 over the whole output, bound 1e-5 (FP32
+against FP64); the measured error is printed for every case.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_util import TOL, dev, host, rel_l2, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def F():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2506_15437_amd as F
+    return F
+
+
+def _check(F, x, direction, tag):
+    y = host(F.fft2(dev(x)) if direction == -1 else F.ifft2(dev(x)))
+    ref = oracle.fft2_forward(x) if direction == -1 else oracle.ifft2(x)
+    err = rel_l2(y, ref)
+    say("%s rel_l2=%.3e" % (tag, err))
+    assert err <= TOL, (tag, err)
+    return y, err
+
+
+def test_64x64_forward_vs_oracle_and_direct(F):
+    say("case 64x64 forward seed 0")
+    x = synth.complex_grid(0, (64, 64))
+    y, _ = _check(F, x, -1, "64x64 fwd")
+    direct = oracle.dft2d_direct(x.astype(np.complex128))
+    err = rel_l2(y, direct)
+    say("64x64 vs direct DFT rel_l2=%.3e" % err)
+    assert err <= TOL
+
+
+SHAPES = [(1, 1), (1, 2), (2, 1), (2, 2), (4, 8), (8, 4), (16, 16), (32, 64), (64, 32), (128, 128), (256, 512),
+          (512, 256), (1024, 64), (64, 1024), (2048, 32), (32, 2048), (4096, 8), (8, 4096), (8192, 4), (4, 8192),
+          (16384, 2), (2, 16384), (1, 16384), (16384, 1), (1, 64), (64, 1), (1024, 1024)]
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "%dx%d" % s)
+def test_shapes_forward_inverse(F, shape):
+    say("case shape %dx%d" % shape)
+    x = synth.complex_grid(hash(shape) % 1000, shape)
+    _check(F, x, -1, "%dx%d fwd" % shape)
+    _check(F, x, +1, "%dx%d inv" % shape)
+
+
+@pytest.mark.parametrize("batch,shape", [(3, (16, 64)), (5, (8, 256)), (7, (64, 16)), (3, (2, 2048)), (2, (128, 4096)),
+                                         (3, (4096, 2)), (5, (1, 512)), (9, (32, 1))])
+def test_ragged_batches(F, batch, shape):
+    """Batches whose vector count leaves the last workgroup partly empty."""
+    say("case batch %d shape %dx%d" % ((batch,) + shape))
+    x = synth.complex_grid(batch, (batch,) + shape)
+    _check(F, x, -1, "b%d %dx%d fwd" % ((batch,) + shape))
+    _check(F, x, +1, "b%d %dx%d inv" % ((batch,) + shape))
+
+
+def test_4096_round_trip(F):
+    """4096 x 4096 forward + inverse (128 MiB), the plain path."""
+    say("case 4096x4096 round trip seed 1")
+    x = synth.complex_grid(1, (4096, 4096))
+    xd = dev(x)
+    yd = F.fft2(xd)
+    y = host(yd)
+    ref = oracle.fft2_forward(x)
+    err_f = rel_l2(y, ref)
+    say("4096^2 fwd rel_l2=%.3e" % err_f)
+    assert err_f <= TOL
+    zd = F.ifft2(yd)
+    err_rt = rel_l2(host(zd), x)
+    say("4096^2 round trip rel_l2=%.3e" % err_rt)
+    assert err_rt <= TOL
+    err_i = rel_l2(host(zd), oracle.ifft2(y))
+    say("4096^2 inv (of GPU fwd) rel_l2=%.3e" % err_i)
+    assert err_i <= TOL
+
+
+@pytest.mark.parametrize("shape,seed", [((8192, 8192), 2), ((16384, 2048), 3)], ids=["8192x8192", "16384x2048"])
+def test_large_forward(F, shape, seed):
+    say("case %dx%d forward seed %d" % (shape + (seed,)))
+    x = synth.complex_grid(seed, shape)
+    _check(F, x, -1, "%dx%d fwd" % shape)
+
+
+def test_in_place_matches_out_of_place_and_is_deterministic(F):
+    import torch
+    say("case in-place 512x1024")
+    x = synth.complex_grid(8, (512, 1024))
+    a = F.fft2(dev(x))
+    b = F.fft2(dev(x))
+    c = dev(x)
+    F.fft2(c, out=c)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    assert torch.equal(a, c)
+
+
+def test_rejects_bad_tensors(F):
+    import torch
+    with pytest.raises(TypeError):
+        F.fft2(torch.zeros(8, 8, dtype=torch.complex128, device="cuda"))
+    with pytest.raises(TypeError):
+        F.fft2(torch.zeros(8, 8, dtype=torch.complex64))
+    with pytest.raises(ValueError):
+        F.fft2(torch.zeros(6, 8, dtype=torch.complex64, device="cuda"))
+
+
+def test_abi_errors_on_device_pointers(F):
+    import torch
+    say("case ABI errors")
+    x = torch.zeros(4, 64, 64, dtype=torch.complex64, device="cuda")
+    p = F.get_plan(4, 64, 64, x.device)
+    base = x.data_ptr()
+    with pytest.raises(F.Fft2dError) as e:
+        F.fft2d_exec(p.handle, base + 4, base + 4, -1, 0)
+    assert e.value.status == 4
+    with pytest.raises(F.Fft2dError) as e:
+        F.fft2d_exec(p.handle, base, base + 8 * 64, -1, 0)
+    assert e.value.status == 9
+    with pytest.raises(F.Fft2dError) as e:
+        F.fft2d_exec(p.handle, base, base, 2, 0)
+    assert e.value.status == 3
+    with pytest.raises(F.Fft2dError) as e:
+        F.fft2d_exec_batched(p.handle, [base], [base], -1, 0)
+    assert e.value.status == 5
+    q = F.fft2d_plan(1, 8, 8)
+    F.fft2d_destroy(q)
+    with pytest.raises(F.Fft2dError) as e:
+        F.fft2d_exec(q, base, base, -1, 0)
+    assert e.value.status == 8
+    assert "C=" in p.describe()
