@@ -58,11 +58,11 @@ def time_plain(F, torch, rows, cols, steps, warmup, seed):
         if evs: evs[0].record(stream)
         F.fft2d_exec_pass(plan.handle, xp, yp, F.FORWARD, 0, sh)
         if evs: evs[1].record(stream)
-        F.fft2d_exec_pass(plan.handle, yp, yp, F.FORWARD, 1, sh)
+        F.fft2d_exec_pass(plan.handle, xp, yp, F.FORWARD, 1, sh)
         if evs: evs[2].record(stream)
         F.fft2d_exec_pass(plan.handle, yp, zp, F.INVERSE, 0, sh)
         if evs: evs[3].record(stream)
-        F.fft2d_exec_pass(plan.handle, zp, zp, F.INVERSE, 1, sh)
+        F.fft2d_exec_pass(plan.handle, yp, zp, F.INVERSE, 1, sh)
         if evs: evs[4].record(stream)
 
     for _ in range(warmup):

@@ -27,9 +27,10 @@
  * nothing is enqueued, outputs are untouched, and fft2d_last_error() gives a
  * thread-local detail string.
  *
- * Thread safety: a uniform plan is read-only during execution and may be used
- * from several host threads and streams at once. A batched plan owns mutable
- * device state (work counters, descriptor table): use it from one stream at a
+ * Thread safety: a plain uniform plan is read-only during execution and may be
+ * used from several host threads and streams at once. A split plan (large
+ * grids; see fft2d_plan) and a batched plan own mutable device memory (work
+ * buffer; work counters and descriptor table): use each from one stream at a
  * time.
  */
 #ifndef FFT2D_H
@@ -73,7 +74,13 @@ typedef struct fft2d_plan_s* fft2d_plan_t;
  * Builds the FP32 twiddle tables (each entry computed in FP64 from its own
  * angle and rounded once; the paper precomputes its twiddles at start-up,
  * Section 4) in device memory on the current HIP device, and chooses the radix
- * schedule and tile shape for each pass. Must be called with a GPU present.
+ * schedule and tile shape for each pass. Grids of at least 2^22 points with
+ * 1024 <= cols <= 8192 use a split column transform (rows = M1 * M2: the row
+ * pass also applies the first M1-point stage of the column FFT, the column pass
+ * the remaining length-M2 stage), which needs a plan-owned work buffer of
+ * batch*rows*cols complex64 points; the environment variable FFT2D_SPLIT
+ * (off | auto | M1) overrides the choice at plan time. Must be called with a
+ * GPU present.
  */
 fft2d_status fft2d_plan(fft2d_plan_t* out, int64_t batch, int64_t rows, int64_t cols);
 
@@ -124,13 +131,16 @@ fft2d_status fft2d_backward(fft2d_plan_t plan, const void* grad_out, void* grad_
 
 /*
  * fft2d_exec_pass -- enqueue only one of the two passes of fft2d_exec, for
- * profiling and per-pass timing: pass 0 is the row pass (length-cols FFT along
- * every row), pass 1 the column pass (length-rows FFT down every column).
- * fft2d_exec(in, out) is exactly pass 0 (in -> out) followed by pass 1
- * (out -> out). The inverse's 1/(M N) scale is applied by the column pass (by
- * the row pass when rows == 1). Returns FFT2D_ERR_INVALID_SIZE if the plan has
- * no such pass (that dimension has length 1) and FFT2D_ERR_INVALID_DIRECTION
- * for a pass index other than 0 or 1. Uniform plans only.
+ * profiling and per-pass timing. Pass 0 is the row pass (length-cols FFT along
+ * every row; for split plans also the first, M1-point stage of the column
+ * transform), pass 1 the column pass. Pass 0 reads `in` and writes the
+ * intermediate result; pass 1 reads the intermediate and writes `out`. The
+ * intermediate is the plan's work buffer for split plans and `out` otherwise,
+ * so pass 0 then pass 1 with the same arguments is exactly fft2d_exec. The
+ * inverse's 1/(M N) scale is applied by the last pass. Returns
+ * FFT2D_ERR_INVALID_SIZE if the plan has no such pass (that dimension has
+ * length 1) and FFT2D_ERR_INVALID_DIRECTION for a pass index other than 0 or 1.
+ * Uniform plans only.
  */
 fft2d_status fft2d_exec_pass(fft2d_plan_t plan, const void* in, void* out, int direction, int pass, void* stream);
 

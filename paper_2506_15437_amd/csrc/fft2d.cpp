@@ -12,6 +12,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -42,16 +43,42 @@ bool pow2_in_range(int64_t n) { return n >= 1 && n <= FFT2D_MAX_LEN && (n & (n -
 
 enum PlanKind { kUniform = 1, kBatched = 2 };
 
+// Number of rows M1 that the row pass combines for a split column transform
+// (1 = plain two-pass transform). Large grids split so that the row pass holds
+// M1 rows of 128 KiB in total and the column pass works on columns of
+// rows / M1 points in 16-column tiles. FFT2D_SPLIT=off|auto|<M1> overrides.
+int64_t choose_split(int64_t rows, int64_t cols) {
+  auto usable = [&](int64_t m1) {
+    return m1 > 1 && rows % m1 == 0 && rows / m1 >= 2 && fft2d::find_combine_kernel((int)cols, (int)m1) &&
+           (fft2d::find_split_column_kernel((int)(rows / m1)) || fft2d::find_pass_kernel((int)(rows / m1), true));
+  };
+  const char* env = std::getenv("FFT2D_SPLIT");
+  if (env && std::strcmp(env, "off") == 0) return 1;
+  if (env && std::strcmp(env, "auto") != 0 && *env) {
+    const int64_t m1 = std::atoll(env);
+    return usable(m1) ? m1 : 1;
+  }
+  if (rows * cols < (int64_t(1) << 22) || cols > 8192) return 1;
+  const int64_t m1 = 16384 / cols;
+  return usable(m1) ? m1 : 1;
+}
+
 }  // namespace
 
 struct fft2d_plan_s {
   int kind = kUniform;
   int device = 0;
   int64_t batch = 0, rows = 0, cols = 0;
+  // Plain transform (m1 == 1): row pass in -> out, column pass out -> out.
+  // Split transform (m1 > 1, rows = m1 * m2): row pass with an m1-point
+  // combine in -> work, then a column pass of length m2 work -> out.
+  int64_t m1 = 1, m2 = 0;
   const PassKernel* row_k = nullptr;  // length-cols FFT along rows (null if cols == 1)
-  const PassKernel* col_k = nullptr;  // length-rows FFT down columns (null if rows == 1)
+  const PassKernel* col_k = nullptr;  // length-rows (or m2) FFT down columns (null if rows == 1)
   float2* tw_row = nullptr;
   float2* tw_col = nullptr;
+  float2* tw_comb = nullptr;  // W_rows^j, j < rows (split transforms)
+  float2* work = nullptr;     // batch*rows*cols points (split transforms)
   BatchedPlan* batched = nullptr;
 };
 
@@ -98,6 +125,26 @@ hipError_t upload_twiddles(const PassKernel& k, float2** dev) {
   return e;
 }
 
+hipError_t upload_root_table(int64_t n, float2** dev) {
+  // w[j] = exp(-2 pi i j / n), j < n, each from its own FP64 cos/sin.
+  std::vector<float2> host((size_t)n);
+  for (int64_t j = 0; j < n; ++j) {
+    const double a = 2.0 * M_PI * (double)j / (double)n;
+    host[(size_t)j] = make_float2((float)std::cos(a), (float)(-std::sin(a)));
+  }
+  hipError_t e = hipMalloc((void**)dev, (size_t)n * sizeof(float2));
+  if (e != hipSuccess) {
+    *dev = nullptr;
+    return e;
+  }
+  e = hipMemcpy(*dev, host.data(), (size_t)n * sizeof(float2), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(*dev);
+    *dev = nullptr;
+  }
+  return e;
+}
+
 // Enqueue the row pass then the column pass of `batch` grids of rows x cols
 // (only_pass = 0 or 1 restricts it to one of them).
 fft2d_status run_uniform(const fft2d_plan_s* p, const float2* in, float2* out, int sign, float scale,
@@ -108,7 +155,39 @@ fft2d_status run_uniform(const fft2d_plan_s* p, const float2* in, float2* out, i
     e = launch_scale_copy(in, out, npts, scale, s);
     return e == hipSuccess ? FFT2D_OK : hip_fail(e, "scale copy launch");
   }
-  const float2* src = in;
+  if (p->m1 > 1) {
+    if (only_pass != 1) {
+      PassArgs a{};
+      a.in = in;
+      a.out = p->work;
+      a.tw = p->tw_row;
+      a.twc = p->tw_comb;
+      a.nvec = p->batch * p->rows;
+      a.ncols = p->cols;
+      a.m1 = p->m1;
+      a.m2 = p->m2;
+      a.scale = 1.0f;
+      a.nblocks = (int)(p->batch * p->m2);
+      e = p->row_k->launch(a, sign, s);
+      if (e != hipSuccess) return hip_fail(e, "row pass (combine) launch");
+    }
+    if (only_pass != 0) {
+      PassArgs a{};
+      a.in = p->work;
+      a.out = out;
+      a.tw = p->tw_col;
+      a.nvec = p->batch * p->m1 * p->cols;
+      a.ncols = p->cols;
+      a.m1 = p->m1;
+      a.m2 = p->m2;
+      a.scale = scale;
+      a.nblocks = pass_blocks(*p->col_k, a.nvec);
+      e = p->col_k->launch(a, sign, s);
+      if (e != hipSuccess) return hip_fail(e, "column pass launch");
+    }
+    return FFT2D_OK;
+  }
+  const float2* src = only_pass == 1 ? out : in;
   if (p->row_k && only_pass != 1) {
     PassArgs a{};
     a.in = src;
@@ -116,6 +195,7 @@ fft2d_status run_uniform(const fft2d_plan_s* p, const float2* in, float2* out, i
     a.tw = p->tw_row;
     a.nvec = p->batch * p->rows;
     a.ncols = p->cols;
+    a.m1 = 1;
     a.scale = p->col_k ? 1.0f : scale;
     a.nblocks = pass_blocks(*p->row_k, a.nvec);
     e = p->row_k->launch(a, sign, s);
@@ -129,6 +209,7 @@ fft2d_status run_uniform(const fft2d_plan_s* p, const float2* in, float2* out, i
     a.tw = p->tw_col;
     a.nvec = p->batch * p->cols;
     a.ncols = p->cols;
+    a.m1 = 1;
     a.scale = scale;
     a.nblocks = pass_blocks(*p->col_k, a.nvec);
     e = p->col_k->launch(a, sign, s);
@@ -150,6 +231,8 @@ void free_plan(fft2d_plan_s* p) {
   if (!p) return;
   if (p->tw_row) (void)hipFree(p->tw_row);
   if (p->tw_col) (void)hipFree(p->tw_col);
+  if (p->tw_comb) (void)hipFree(p->tw_comb);
+  if (p->work) (void)hipFree(p->work);
   if (p->batched) destroy_batched(p->batched);
   delete p;
 }
@@ -187,19 +270,32 @@ fft2d_status fft2d_plan(fft2d_plan_t* out, int64_t batch, int64_t rows, int64_t 
     delete p;
     return hip_fail(e, "hipGetDevice");
   }
-  if (cols > 1) p->row_k = find_pass_kernel((int)cols, false);
-  if (rows > 1) p->col_k = find_pass_kernel((int)rows, true);
+  p->m1 = choose_split(rows, cols);
+  p->m2 = rows / p->m1;
+  if (p->m1 > 1) {
+    p->row_k = find_combine_kernel((int)cols, (int)p->m1);
+    p->col_k = find_split_column_kernel((int)p->m2);
+    if (!p->col_k) p->col_k = find_pass_kernel((int)p->m2, true);
+  } else {
+    if (cols > 1) p->row_k = find_pass_kernel((int)cols, false);
+    if (rows > 1) p->col_k = find_pass_kernel((int)rows, true);
+  }
   if ((cols > 1 && !p->row_k) || (rows > 1 && !p->col_k)) {
     delete p;
     return fail(FFT2D_ERR_INVALID_SIZE, "no kernel for this length");
   }
-  if (p->row_k && (e = upload_twiddles(*p->row_k, &p->tw_row)) != hipSuccess) {
+  auto oom_or_hip = [&](hipError_t err, const char* what) {
     free_plan(p);
-    return e == hipErrorOutOfMemory ? fail(FFT2D_ERR_OUT_OF_MEMORY, "twiddle table") : hip_fail(e, "twiddle upload");
-  }
-  if (p->col_k && (e = upload_twiddles(*p->col_k, &p->tw_col)) != hipSuccess) {
-    free_plan(p);
-    return e == hipErrorOutOfMemory ? fail(FFT2D_ERR_OUT_OF_MEMORY, "twiddle table") : hip_fail(e, "twiddle upload");
+    return err == hipErrorOutOfMemory ? fail(FFT2D_ERR_OUT_OF_MEMORY, what) : hip_fail(err, what);
+  };
+  if (p->row_k && (e = upload_twiddles(*p->row_k, &p->tw_row)) != hipSuccess) return oom_or_hip(e, "twiddle table");
+  if (p->col_k && (e = upload_twiddles(*p->col_k, &p->tw_col)) != hipSuccess) return oom_or_hip(e, "twiddle table");
+  if (p->m1 > 1) {
+    if ((e = upload_root_table(rows, &p->tw_comb)) != hipSuccess) return oom_or_hip(e, "twiddle table");
+    if ((e = hipMalloc((void**)&p->work, (size_t)(batch * rows * cols) * sizeof(float2))) != hipSuccess) {
+      p->work = nullptr;
+      return oom_or_hip(e, "work buffer");
+    }
   }
   {
     std::lock_guard<std::mutex> g(g_plans_mu);
@@ -337,12 +433,14 @@ fft2d_status fft2d_plan_describe(fft2d_plan_t plan, char* buf, int64_t buflen) {
     std::string s = "L=" + std::to_string(k->L) + " radix=";
     for (int i = 0; i < k->npass; ++i) s += (i ? "x" : "") + std::to_string(k->radix[i]);
     s += " E=" + std::to_string(k->E) + " C=" + std::to_string(k->C) + " Q=" + std::to_string(k->Q) +
-         " threads=" + std::to_string(k->threads) + " lds=" + std::to_string(k->lds_bytes);
+         " threads=" + std::to_string(k->threads) + " lds=" + std::to_string(k->lds_bytes) +
+         (k->wpe > 1 ? " wpe=" + std::to_string(k->wpe) : "");
     return s;
   };
   if (plan->kind == kUniform) {
     d = "uniform batch=" + std::to_string(plan->batch) + " " + std::to_string(plan->rows) + "x" +
-        std::to_string(plan->cols) + " row[" + desc(plan->row_k) + "] col[" + desc(plan->col_k) + "]";
+        std::to_string(plan->cols) + " split=" + std::to_string(plan->m1) + " row[" + desc(plan->row_k) +
+        (plan->m1 > 1 ? " combine" : "") + "] col[" + desc(plan->col_k) + "]";
   } else {
     d = describe_batched(plan->batched);
   }

@@ -14,12 +14,23 @@ constexpr int kMaxPasses = 6;
 // vectors. Row mode: vector v is the L contiguous points starting at v*L.
 // Column mode: vector v = g*ncols + col is column `col` of grid g, its element
 // e at g*L*ncols + e*ncols + col (stride ncols points).
+//
+// Split column transform (M = M1 * M2). A row pass with combine handles, per
+// workgroup, the M1 rows M2*m1 + m2 (m1 < M1) of one grid: it transforms each
+// row, applies an M1-point DFT across them (m1 -> k1), multiplies output k1 by
+// W_M^(m2 k1) and stores it to row M2*k1 + m2. A column pass with m1 = M1 then
+// transforms length-M2 columns of the row block [M2*k1, M2*k1 + M2) and
+// stores element k2 to row k1 + M1*k2. Together they are the length-M column
+// DFT (four-step factorisation); m1 = 1 is the plain column pass.
 struct PassArgs {
   const float2* in;
   float2* out;
   const float2* tw;   // inter-pass twiddle table of this pass kernel's schedule
+  const float2* twc;  // row pass with combine: W_M^j for j < M
   int64_t nvec;       // number of vectors
   int64_t ncols;      // column mode: points per row (N); unused in row mode
+  int64_t m1;         // column mode: M1 of a split transform (1 = plain)
+  int64_t m2;         // row pass with combine: M2 = M / M1
   float scale;        // multiplies every output point
   int nblocks;        // grid size (for the XCD-aware block remap)
 };
@@ -30,6 +41,8 @@ struct PassArgs {
 struct PassKernel {
   int L, E, T, C, Q, threads;
   int colmode;
+  int combine;  // row pass with an M1 = C point combine across its rows (split column transform)
+  int wpe;  // minimum waves per SIMD the kernel was compiled for
   int npass;
   int radix[kMaxPasses];
   size_t lds_bytes;
@@ -38,6 +51,10 @@ struct PassKernel {
 
 // Default kernel for a length L in [2, 16384] (power of two); nullptr otherwise.
 const PassKernel* find_pass_kernel(int L, bool colmode);
+// Row pass with an M1-point combine across M1 rows of length L (nullptr if none).
+const PassKernel* find_combine_kernel(int L, int m1);
+// Column pass for the length-M2 columns of a split transform.
+const PassKernel* find_split_column_kernel(int L);
 // All compiled variants for a length (for the autotuner); returns the count.
 int list_pass_kernels(int L, bool colmode, const PassKernel** out, int cap);
 

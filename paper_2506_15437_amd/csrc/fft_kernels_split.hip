@@ -1,0 +1,45 @@
+// Kernel tables of split column transforms: row passes with an M1-point combine and the
+// column passes of length rows/M1.
+#include "fft_pass.hpp"
+#include "fft_tables.h"
+
+namespace fft2d {
+
+using namespace dev;
+
+namespace {
+
+// Row passes with an M1-point combine (split column transforms): M1 rows of
+// length L per workgroup, 128 KiB of data, 512 threads, 68 KiB of LDS.
+using RC8192x2 = Cfg<8192, 32, 2, 2, false, 16, 16, 32>;
+using RC4096x4 = Cfg<4096, 32, 4, 2, false, 16, 16, 16>;
+using RC2048x8 = Cfg<2048, 32, 8, 2, false, 16, 16, 8>;
+using RC1024x16 = Cfg<1024, 32, 16, 2, false, 16, 16, 4>;
+
+// Column passes of split transforms: 16 columns (128-byte row segments).
+using S512 = Cfg<512, 32, 16, 2, true, 16, 32>;
+using S1024 = Cfg<1024, 32, 16, 2, true, 16, 16, 4>;
+using S2048 = Cfg<2048, 32, 16, 2, true, 16, 16, 8>;
+using S4096 = Cfg<4096, 32, 8, 2, true, 16, 16, 16>;
+
+const PassKernel kCombineKernels[] = {
+    describe<RC8192x2, true, 4>(), describe<RC4096x4, true, 4>(), describe<RC2048x8, true, 4>(),
+    describe<RC1024x16, true, 4>(),
+};
+const PassKernel kSplitColKernels[] = {
+    describe<S512>(), describe<S1024>(), describe<S2048>(), describe<S4096>(),
+};
+
+}  // namespace
+
+const PassKernel* combine_kernel_table(int* count) {
+  *count = (int)(sizeof(kCombineKernels) / sizeof(kCombineKernels[0]));
+  return kCombineKernels;
+}
+
+const PassKernel* split_col_kernel_table(int* count) {
+  *count = (int)(sizeof(kSplitColKernels) / sizeof(kSplitColKernels[0]));
+  return kSplitColKernels;
+}
+
+}  // namespace fft2d

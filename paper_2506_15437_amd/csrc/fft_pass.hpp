@@ -1,0 +1,461 @@
+// HIP kernels for gfx950 (MI355X): one pass of a batched complex FFT of
+// power-of-two length L, applied along rows (contiguous vectors) or down
+// columns (vectors strided by the row length).
+//
+// Algorithm. The paper's FFT (Section 2.2, Listing 1, Fig. 2) is radix-2
+// Cooley-Tukey by decimation in time: bit-reversal reordering, then log2 L
+// butterfly steps whose span doubles each step, each butterfly computing
+// f = d1 * w, d1 = d0 - f, d0 = d0 + f with a precomputed twiddle w. Here the
+// log2 L steps are grouped into a few passes of radix R = 2^s:
+//   * inside a pass, each thread holds R points in registers and runs s
+//     radix-2 DIT steps on them, on bit-reversed register order (the
+//     bit-reversal is a renaming of registers, free at run time; the in-pass
+//     twiddles W_2^q ... W_R^q are compile-time constants evaluated in double
+//     precision and rounded once);
+//   * between passes, the points are multiplied by the inter-pass twiddles
+//     W_{Ns R}^{k r} (FP32 table, computed in FP64 on the host) and written
+//     back through LDS directly into the order the next pass reads (a Stockham
+//     auto-sort), which is the paper's "one data reordering per step" idea
+//     (Section 4, Fig. 5) moved on-chip: the digit reversal of the whole
+//     transform costs no HBM traffic at all.
+// Each pass kernel therefore reads every point from HBM once, coalesced, and
+// writes it once, coalesced (first pass loads point tt + T*j into register j,
+// the last pass stores register j to point tt + T*j).
+//
+// Pass p (radix R, Ns = product of the earlier radices) in Stockham form:
+// butterfly b in [0, L/R) takes points b + r L/R (r < R), multiplies point r
+// by W_{Ns R}^{(b mod Ns) r}, transforms the R points, and sends output s to
+// position (b div Ns) Ns R + (b mod Ns) + s Ns.
+//
+// Column mode: a workgroup owns C adjacent columns; lanes run over the
+// columns first, so each load/store instruction touches rows of C*8 bytes.
+// Column workgroups are remapped so that each of the 8 XCDs (each with its own
+// L2) works through a contiguous range of column tiles; neighbouring tiles
+// share cache lines and are then served by the same L2.
+#pragma once
+
+#include "fft_internal.h"
+
+#include <type_traits>
+
+namespace fft2d {
+namespace dev {
+
+// ---------------------------------------------------------------- utilities
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
+
+constexpr int ilog2c(int n) { return n <= 1 ? 0 : 1 + ilog2c(n >> 1); }
+
+template <int R>
+constexpr int bitrev(int x) {
+  int r = 0;
+  for (int b = 1; b < R; b <<= 1) {
+    r = (r << 1) | (x & 1);
+    x >>= 1;
+  }
+  return r;
+}
+
+// Compile-time cos/sin of 2 pi q / n in double precision: the angle is
+// reduced to an octant in integers, then a Taylor series on [0, pi/4].
+constexpr double kQuarterPi = 0.78539816339744830961566084581988;
+
+constexpr double series_sin(double x) {
+  double term = x, sum = x;
+  for (int k = 1; k < 14; ++k) {
+    term *= -x * x / ((2.0 * k) * (2.0 * k + 1.0));
+    sum += term;
+  }
+  return sum;
+}
+constexpr double series_cos(double x) {
+  double term = 1.0, sum = 1.0;
+  for (int k = 1; k < 14; ++k) {
+    term *= -x * x / ((2.0 * k - 1.0) * (2.0 * k));
+    sum += term;
+  }
+  return sum;
+}
+
+struct CosSin {
+  double c, s;
+};
+
+constexpr CosSin unit_root(long q, long n) {
+  q %= n;
+  if (q < 0) q += n;
+  const long o = (8 * q) / n;        // octant of 2 pi q / n
+  const long rem = 8 * q - o * n;    // angle inside the octant: (pi/4) rem / n
+  double cphi = 0.0, sphi = 0.0;     // angle inside the quadrant
+  if ((o & 1) == 0) {
+    const double a = kQuarterPi * (double)rem / (double)n;
+    cphi = series_cos(a);
+    sphi = series_sin(a);
+  } else {
+    const double b = kQuarterPi * (double)(n - rem) / (double)n;  // pi/2 - phi
+    cphi = series_sin(b);
+    sphi = series_cos(b);
+  }
+  switch (o >> 1) {
+    case 0: return {cphi, sphi};
+    case 1: return {-sphi, cphi};
+    case 2: return {-cphi, -sphi};
+    default: return {sphi, -cphi};
+  }
+}
+
+typedef float f2v __attribute__((ext_vector_type(2)));
+
+// Global loads/stores of one complex64; NT selects the nontemporal (streaming) form.
+template <bool NT>
+__device__ __forceinline__ float2 gload(const float2* p) {
+  if constexpr (NT) {
+    const f2v v = __builtin_nontemporal_load(reinterpret_cast<const f2v*>(p));
+    return make_float2(v.x, v.y);
+  } else {
+    return *p;
+  }
+}
+template <bool NT>
+__device__ __forceinline__ void gstore(float2* p, float2 v) {
+  if constexpr (NT) {
+    f2v w;
+    w.x = v.x;
+    w.y = v.y;
+    __builtin_nontemporal_store(w, reinterpret_cast<f2v*>(p));
+  } else {
+    *p = v;
+  }
+}
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// v * exp(DIR * 2 pi i Q / N), with the trivial rotations done by swaps.
+template <int DIR, int N, int Q>
+__device__ __forceinline__ float2 rotate(float2 v) {
+  constexpr int q = ((Q % N) + N) % N;
+  if constexpr (q == 0) {
+    return v;
+  } else if constexpr (2 * q == N) {
+    return make_float2(-v.x, -v.y);
+  } else if constexpr (4 * q == N) {  // exp(DIR i pi / 2) = DIR i
+    if constexpr (DIR < 0) return make_float2(v.y, -v.x);
+    else return make_float2(-v.y, v.x);
+  } else if constexpr (4 * q == 3 * N) {  // = -DIR i
+    if constexpr (DIR < 0) return make_float2(-v.y, v.x);
+    else return make_float2(v.y, -v.x);
+  } else {
+    constexpr CosSin w = unit_root(q, N);
+    constexpr float c = (float)w.c;
+    constexpr float s = (float)(DIR * w.s);
+    return make_float2(v.x * c - v.y * s, v.x * s + v.y * c);
+  }
+}
+
+// In-register R-point DFT (exponent sign DIR), natural order in and out,
+// computed as log2 R radix-2 decimation-in-time steps on bit-reversed data:
+// at the step of span h, points lo and lo + h (lo mod h = q) combine with the
+// twiddle W_{2h}^q.
+template <int R, int DIR>
+__device__ __forceinline__ void dft(float2 (&a)[R]) {
+  float2 b[R];
+  static_for<0, R>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    b[bitrev<R>(i)] = a[i];
+  });
+  static_for<0, ilog2c(R)>([&](auto S) {
+    constexpr int h = 1 << decltype(S)::value;
+    static_for<0, R / (2 * h)>([&](auto G) {
+      static_for<0, h>([&](auto Qv) {
+        constexpr int q = decltype(Qv)::value;
+        constexpr int lo = decltype(G)::value * 2 * h + q;
+        constexpr int hi = lo + h;
+        const float2 f = rotate<DIR, 2 * h, q>(b[hi]);
+        b[hi] = csub(b[lo], f);
+        b[lo] = cadd(b[lo], f);
+      });
+    });
+  });
+  static_for<0, R>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    a[i] = b[i];
+  });
+}
+
+// ------------------------------------------------------------ configuration
+template <int L_, int E_, int C_, int Q_, bool COL_, int... Rs>
+struct Cfg {
+  static constexpr int L = L_;   // FFT length
+  static constexpr int E = E_;   // points per thread
+  static constexpr int C = C_;   // vectors per workgroup
+  static constexpr int Q = Q_;   // LDS exchange rounds
+  static constexpr bool COL = COL_;
+  static constexpr int P = sizeof...(Rs);
+  static constexpr int T = L / E;  // threads per vector
+  static constexpr int THREADS = T * C;
+  static constexpr int LQ = L / Q;  // points of one vector exchanged per round
+
+  static constexpr int radix(int p) {
+    const int r[] = {Rs...};
+    return r[p];
+  }
+  static constexpr int ns(int p) {
+    int v = 1;
+    for (int q = 0; q < p; ++q) v *= radix(q);
+    return v;
+  }
+  static constexpr int tw_off(int p) {
+    int o = 0;
+    for (int q = 1; q < p; ++q) o += ns(q) * (radix(q) - 1);
+    return o;
+  }
+  static constexpr int pad(int e) { return e + (e >> 4); }
+  static constexpr int LQP = pad(LQ - 1) + 1;
+  // Row mode: consecutive vectors of one wave start T banks-pairs apart.
+  static constexpr int ROWSTRIDE = (T >= 32) ? LQP : (LQP + T);
+  static constexpr int LDS_ELEMS = (P > 1) ? (COL ? LQP * C : ROWSTRIDE * C) : 1;
+
+  __device__ static __forceinline__ int lds_index(int c, int e) {
+    if constexpr (COL) return pad(e) * C + c;
+    else return c * ROWSTRIDE + pad(e);
+  }
+
+  static constexpr bool valid() {
+    int prod = 1;
+    for (int p = 0; p < P; ++p) {
+      if (E % radix(p) != 0) return false;
+      prod *= radix(p);
+    }
+    if (prod != L || L % E != 0 || THREADS > 1024 || THREADS % 64 != 0) return false;
+    if (Q > 1) {
+      for (int p = 0; p + 1 < P; ++p) {
+        if ((E / radix(p)) % Q != 0) return false;  // whole butterflies per round
+        if (ns(p) > T) return false;                // destinations of one butterfly stay in one round
+      }
+    }
+    return LDS_ELEMS * 8 <= 160 * 1024;
+  }
+};
+
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+  // Consecutive workgroup ids are dispatched round-robin over the 8 XCDs; give
+  // XCD x the contiguous id range [x q + min(x, r), ...) in dispatch order.
+  const int x = b & 7, i = b >> 3;
+  const int q = nb >> 3, r = nb & 7;
+  return x * q + (x < r ? x : r) + i;
+}
+
+// One pass: butterflies of this thread, then (unless last) the LDS exchange.
+template <class K, int DIR, int p, int SB = 0>
+__device__ __forceinline__ void run_pass(float2 (&d)[K::E], float2* lds, int tt, int c, const float2* __restrict__ tw) {
+  constexpr int R = K::radix(p);
+  constexpr int Ns = K::ns(p);
+  constexpr int NB = K::E / R;
+  constexpr bool last = (p == K::P - 1);
+  float2 o[K::E];
+  static_for<0, NB>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    const int b = tt + K::T * i;
+    float2 x[R];
+    static_for<0, R>([&](auto Rr) {
+      constexpr int r = decltype(Rr)::value;
+      x[r] = d[i + NB * r];
+    });
+    if constexpr (p > 0) {
+      const float2* twp = tw + K::tw_off(p) + (b & (Ns - 1));
+      static_for<1, R>([&](auto Rr) {
+        constexpr int r = decltype(Rr)::value;
+        float2 w = twp[(r - 1) * Ns];
+        if constexpr (DIR > 0) w.y = -w.y;
+        x[r] = cmul(x[r], w);
+      });
+    }
+    dft<R, DIR>(x);
+    static_for<0, R>([&](auto S) {
+      constexpr int s = decltype(S)::value;
+      if constexpr (last) d[i + NB * s] = x[s];
+      else o[i * R + s] = x[s];
+    });
+    // SB: keep the scheduler from hoisting the next butterfly's twiddle loads
+    // above this one (bounds register pressure at some latency cost).
+    if constexpr (SB != 0) __builtin_amdgcn_sched_barrier(0);
+  });
+  if constexpr (!last) {
+    constexpr int NBQ = NB / K::Q;
+    constexpr int EQ = K::E / K::Q;
+    static_for<0, K::Q>([&](auto H) {
+      constexpr int h = decltype(H)::value;
+      static_for<0, NBQ>([&](auto I) {
+        constexpr int i = h * NBQ + decltype(I)::value;
+        const int b = tt + K::T * i;
+        const int dst = (b / Ns) * Ns * R + (b & (Ns - 1)) - h * K::LQ;
+        static_for<0, R>([&](auto S) {
+          constexpr int s = decltype(S)::value;
+          lds[K::lds_index(c, dst + s * Ns)] = o[i * R + s];
+        });
+      });
+      __syncthreads();
+      static_for<0, EQ>([&](auto J) {
+        constexpr int j = h * EQ + decltype(J)::value;
+        d[j] = lds[K::lds_index(c, tt + K::T * j - h * K::LQ)];
+      });
+      __syncthreads();
+    });
+  }
+}
+
+template <class K, int DIR, bool NT = false, int WPE = 1, int SB = 0>
+__global__ __launch_bounds__(K::THREADS) __attribute__((amdgpu_waves_per_eu(WPE))) void pass_kernel(PassArgs a) {
+  static_assert(K::valid(), "invalid pass configuration");
+  __shared__ float2 lds[K::LDS_ELEMS];
+  const int t = threadIdx.x;
+  const int c = K::COL ? (t % K::C) : (t / K::T);
+  const int tt = K::COL ? (t / K::C) : (t % K::T);
+  const int w = K::COL ? xcd_remap(blockIdx.x, a.nblocks) : (int)blockIdx.x;
+  const int64_t v = (int64_t)w * K::C + c;
+  const bool active = v < a.nvec;
+  int64_t base_in, base_out, es_in, es_out;
+  if constexpr (K::COL) {
+    // vector v = (grid g, row block k1, column col); element e of the block
+    // is row M2*k1 + e on input and row k1 + M1*e on output (M2 = L).
+    const int64_t per_g = a.m1 * a.ncols;
+    const int64_t g = v / per_g;
+    const int64_t rem = v - g * per_g;
+    const int64_t k1 = rem / a.ncols;
+    const int64_t col = rem - k1 * a.ncols;
+    const int64_t gbase = g * (int64_t)K::L * per_g;
+    base_in = gbase + k1 * (int64_t)K::L * a.ncols + col;
+    base_out = gbase + k1 * a.ncols + col;
+    es_in = a.ncols;
+    es_out = per_g;
+  } else {
+    base_in = base_out = v * K::L;
+    es_in = es_out = 1;
+  }
+  float2 d[K::E];
+  if (active) {
+    static_for<0, K::E>([&](auto J) {
+      constexpr int j = decltype(J)::value;
+      d[j] = gload<NT>(a.in + base_in + (int64_t)(tt + K::T * j) * es_in);
+    });
+  } else {
+    static_for<0, K::E>([&](auto J) { d[decltype(J)::value] = make_float2(0.f, 0.f); });
+  }
+  static_for<0, K::P>([&](auto Pp) { run_pass<K, DIR, decltype(Pp)::value, SB>(d, lds, tt, c, a.tw); });
+  if (active) {
+    const float sc = a.scale;
+    static_for<0, K::E>([&](auto J) {
+      constexpr int j = decltype(J)::value;
+      gstore<NT>(a.out + base_out + (int64_t)(tt + K::T * j) * es_out, make_float2(d[j].x * sc, d[j].y * sc));
+    });
+  }
+}
+
+// Row pass with combine (first half of a split column transform, see
+// PassArgs): workgroup w = (grid g, m2) transforms the M1 = C rows
+// M2*m1 + m2, then for every column position an M1-point DFT across those rows
+// and the twiddle W_M^(m2 k1), stored to row M2*k1 + m2. The rows' transformed
+// points are exchanged through LDS in Q rounds of L/Q positions; in each round
+// every thread owns L/(Q*THREADS) positions and all M1 rows of each.
+template <class K, int DIR, int WPE = 1, int SB = 0>
+__global__ __launch_bounds__(K::THREADS) __attribute__((amdgpu_waves_per_eu(WPE))) void rowc_kernel(PassArgs a) {
+  static_assert(K::valid() && !K::COL && K::C >= 2 && K::P > 1, "invalid combine configuration");
+  constexpr int M1 = K::C;
+  constexpr int NQ = K::L / K::Q;
+  constexpr int NPOS = NQ / K::THREADS;
+  static_assert(NPOS >= 1 && NQ % K::THREADS == 0, "positions per thread must be whole");
+  __shared__ float2 lds[K::LDS_ELEMS];
+  const int t = threadIdx.x;
+  const int c = t / K::T;
+  const int tt = t % K::T;
+  const int64_t w = blockIdx.x;
+  const int64_t g = w / a.m2;
+  const int64_t m2 = w - g * a.m2;
+  const int64_t gbase = g * a.m2 * M1 * K::L;
+  const float2* src = a.in + gbase + ((int64_t)c * a.m2 + m2) * K::L;
+  float2 d[K::E];
+  static_for<0, K::E>([&](auto J) {
+    constexpr int j = decltype(J)::value;
+    d[j] = src[tt + K::T * j];
+  });
+  static_for<0, K::P>([&](auto Pp) { run_pass<K, DIR, decltype(Pp)::value, SB>(d, lds, tt, c, a.tw); });
+  float2 wk[M1];
+  static_for<1, M1>([&](auto Kk) {
+    constexpr int k1 = decltype(Kk)::value;
+    float2 w1 = a.twc[m2 * k1];
+    if constexpr (DIR > 0) w1.y = -w1.y;
+    wk[k1] = w1;
+  });
+  static_for<0, K::Q>([&](auto H) {
+    constexpr int h = decltype(H)::value;
+    constexpr int EQ = K::E / K::Q;
+    static_for<0, EQ>([&](auto J) {
+      constexpr int j = h * EQ + decltype(J)::value;
+      lds[K::lds_index(c, tt + K::T * j - h * NQ)] = d[j];
+    });
+    __syncthreads();
+    static_for<0, NPOS>([&](auto I) {
+      const int p = t + K::THREADS * decltype(I)::value;
+      float2 x[M1];
+      static_for<0, M1>([&](auto R) {
+        constexpr int r = decltype(R)::value;
+        x[r] = lds[K::lds_index(r, p)];
+      });
+      dft<M1, DIR>(x);
+      float2* dst = a.out + gbase + m2 * K::L + h * NQ + p;
+      static_for<0, M1>([&](auto Kk) {
+        constexpr int k1 = decltype(Kk)::value;
+        dst[(int64_t)k1 * a.m2 * K::L] = (k1 == 0) ? x[0] : cmul(x[k1], wk[k1]);
+      });
+    });
+    __syncthreads();
+  });
+}
+
+template <class K, int WPE>
+hipError_t launch_pass(const PassArgs& a, int dir, hipStream_t s) {
+  if (dir < 0) hipLaunchKernelGGL((pass_kernel<K, -1, false, WPE>), dim3(a.nblocks), dim3(K::THREADS), 0, s, a);
+  else hipLaunchKernelGGL((pass_kernel<K, +1, false, WPE>), dim3(a.nblocks), dim3(K::THREADS), 0, s, a);
+  return hipGetLastError();
+}
+
+template <class K, int WPE>
+hipError_t launch_rowc(const PassArgs& a, int dir, hipStream_t s) {
+  if (dir < 0) hipLaunchKernelGGL((rowc_kernel<K, -1, WPE>), dim3(a.nblocks), dim3(K::THREADS), 0, s, a);
+  else hipLaunchKernelGGL((rowc_kernel<K, +1, WPE>), dim3(a.nblocks), dim3(K::THREADS), 0, s, a);
+  return hipGetLastError();
+}
+
+// WPE: minimum waves per SIMD the compiler must allow (bounds VGPR use).
+template <class K, bool COMBINE = false, int WPE = 1>
+constexpr PassKernel describe() {
+  PassKernel k{};
+  k.combine = COMBINE ? K::C : 0;
+  k.L = K::L;
+  k.E = K::E;
+  k.T = K::T;
+  k.C = K::C;
+  k.Q = K::Q;
+  k.threads = K::THREADS;
+  k.colmode = K::COL ? 1 : 0;
+  k.npass = K::P;
+  for (int p = 0; p < kMaxPasses; ++p) k.radix[p] = p < K::P ? K::radix(p) : 0;
+  k.lds_bytes = (size_t)K::LDS_ELEMS * 8;
+  k.wpe = WPE;
+  if constexpr (COMBINE) k.launch = &launch_rowc<K, WPE>;
+  else k.launch = &launch_pass<K, WPE>;
+  return k;
+}
+
+}  // namespace dev
+}  // namespace fft2d

@@ -141,3 +141,53 @@ def test_abi_errors_on_device_pointers(F):
         F.fft2d_exec(q, base, base, -1, 0)
     assert e.value.status == 8
     assert "C=" in p.describe()
+
+
+# Split column transforms (row pass with an M1-point combine + column pass of
+# length rows/M1), forced at sizes the oracle handles in well under a second.
+SPLIT_CASES = [(1, (32, 1024), 16), (2, (64, 1024), 16), (1, (256, 2048), 8), (3, (64, 2048), 8),
+               (1, (512, 4096), 4), (2, (128, 4096), 4), (1, (64, 8192), 2), (1, (2048, 1024), 16),
+               (1, (8192, 2048), 8)]
+
+
+@pytest.mark.parametrize("batch,shape,m1", SPLIT_CASES, ids=lambda v: str(v))
+def test_split_transform(F, batch, shape, m1, monkeypatch):
+    say("case split batch %d shape %dx%d m1 %d" % ((batch,) + shape + (m1,)))
+    monkeypatch.setenv("FFT2D_SPLIT", str(m1))
+    plan = F.Plan(batch, *shape)
+    try:
+        assert ("split=%d " % m1) in plan.describe(), plan.describe()
+        x = synth.complex_grid(m1 + batch, (batch,) + shape)
+        xd = dev(x)
+        y = host(plan(xd, F.FORWARD))
+        err = rel_l2(y, oracle.fft2_forward(x))
+        say("split fwd rel_l2=%.3e" % err)
+        assert err <= TOL
+        z = host(plan(xd, F.INVERSE))
+        err = rel_l2(z, oracle.ifft2(x))
+        say("split inv rel_l2=%.3e" % err)
+        assert err <= TOL
+        g = host(plan.backward(xd, F.FORWARD))
+        err = rel_l2(g, oracle.adjoint(x, -1))
+        say("split adjoint rel_l2=%.3e" % err)
+        assert err <= TOL
+        # in place through the work buffer
+        w = dev(x)
+        plan(w, F.FORWARD, out=w)
+        assert rel_l2(host(w), y) <= 1e-7
+    finally:
+        plan.close()
+
+
+def test_auto_split_choice(F):
+    say("case auto split choice")
+    import os
+    assert os.environ.get("FFT2D_SPLIT") is None
+    p = F.Plan(1, 4096, 4096)
+    q = F.Plan(1, 64, 64)
+    try:
+        assert "split=4 " in p.describe(), p.describe()
+        assert "split=1 " in q.describe(), q.describe()
+    finally:
+        p.close()
+        q.close()
