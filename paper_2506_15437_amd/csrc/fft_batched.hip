@@ -1,25 +1,665 @@
-// Batched path (placeholder until the persistent kernel lands).
+// Batched path: many 2D FFTs of different power-of-two shapes in ONE
+// persistent kernel launch, replayed from a HIP graph.
+//
+// Work decomposition. Every transform f (rows M, cols N) becomes row items
+// (tiles of C_row(N) rows; the row FFT of length N) and column items (tiles of
+// C_col(M) columns; the column FFT of length M, in place on the output). A
+// 1 x 1 transform is one copy item. The item list puts every row item before
+// the column items of the same transform, in an order chosen by the
+// autotuner. Persistent workgroups pop items from an atomic queue head; a
+// column item of f waits until f's row-item counter reaches its row-item
+// count. Because every row item of f was popped before any column item of f,
+// and row items never wait, the wait always ends, whatever the number of
+// resident workgroups.
+//
+// Publication of a row item's results: every wave waits for its own stores
+// (s_waitcnt), the workgroup synchronises, then one lane increments f's
+// counter with an agent-scope release. The waiting lane reads the counter
+// with agent-scope acquire before the workgroup loads the data.
+//
+// Direction. The kernel always runs the forward sign; the inverse is
+// conj(F(conj(x))) / (M N): row items conjugate on load, column items
+// conjugate and scale on store (exact in floating point).
 #include "fft_batched.h"
+#include "fft_pass.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include <sys/stat.h>
 
 namespace fft2d {
+namespace {
+
+using namespace dev;
+
+constexpr int kThreads = 512;
+constexpr int kNumCfg = 32;  // id = mode * 16 + log2(L); mode 0 = row, 1 = column
+
+// Row configurations (512 threads each).
+using BR2 = Cfg<2, 2, 512, 1, false, 2>;
+using BR4 = Cfg<4, 4, 512, 1, false, 4>;
+using BR8 = Cfg<8, 8, 512, 1, false, 8>;
+using BR16 = Cfg<16, 16, 512, 1, false, 16>;
+using BR32 = Cfg<32, 8, 128, 1, false, 8, 4>;
+using BR64 = Cfg<64, 8, 64, 1, false, 8, 8>;
+using BR128 = Cfg<128, 16, 64, 1, false, 16, 8>;
+using BR256 = Cfg<256, 16, 32, 1, false, 16, 16>;
+using BR512 = Cfg<512, 16, 16, 1, false, 16, 16, 2>;
+using BR1024 = Cfg<1024, 16, 8, 1, false, 16, 16, 4>;
+using BR2048 = Cfg<2048, 16, 4, 1, false, 16, 16, 8>;
+using BR4096 = Cfg<4096, 16, 2, 1, false, 16, 16, 16>;
+using BR8192 = Cfg<8192, 16, 1, 1, false, 16, 16, 16, 2>;
+using BR16384 = Cfg<16384, 32, 1, 2, false, 16, 16, 16, 4>;
+// Column configurations (512 threads each).
+using BC2 = Cfg<2, 2, 512, 1, true, 2>;
+using BC4 = Cfg<4, 4, 512, 1, true, 4>;
+using BC8 = Cfg<8, 8, 512, 1, true, 8>;
+using BC16 = Cfg<16, 16, 512, 1, true, 16>;
+using BC32 = Cfg<32, 8, 128, 1, true, 8, 4>;
+using BC64 = Cfg<64, 8, 64, 1, true, 8, 8>;
+using BC128 = Cfg<128, 16, 64, 1, true, 16, 8>;
+using BC256 = Cfg<256, 16, 32, 1, true, 16, 16>;
+using BC512 = Cfg<512, 32, 32, 2, true, 16, 32>;
+using BC1024 = Cfg<1024, 32, 16, 2, true, 16, 16, 4>;
+using BC2048 = Cfg<2048, 32, 8, 2, true, 16, 16, 8>;
+using BC4096 = Cfg<4096, 32, 4, 2, true, 16, 16, 16>;
+using BC8192 = Cfg<8192, 32, 2, 2, true, 16, 16, 32>;
+using BC16384 = Cfg<16384, 32, 1, 2, true, 16, 16, 16, 4>;
+
+template <class... Ks>
+constexpr int max_lds() {
+  int m = 1;
+  ((m = Ks::LDS_ELEMS > m ? Ks::LDS_ELEMS : m), ...);
+  return m;
+}
+constexpr int kLdsElems = max_lds<BR2, BR4, BR8, BR16, BR32, BR64, BR128, BR256, BR512, BR1024, BR2048, BR4096,
+                                  BR8192, BR16384, BC2, BC4, BC8, BC16, BC32, BC64, BC128, BC256, BC512, BC1024,
+                                  BC2048, BC4096, BC8192, BC16384>();
+static_assert(kLdsElems * 8 <= 80 * 1024, "two batched workgroups must fit one CU's LDS");
+
+struct BatchDesc {
+  const float2* in;
+  float2* out;
+  int32_t rows, cols;
+  int32_t row_cfg, col_cfg;
+  int32_t nrow_items;
+  int32_t pad;
+};
+
+enum ItemKind { kRowItem = 0, kColItem = 1, kCopyItem = 2 };
+
+struct BatchArgs {
+  const BatchDesc* desc;
+  const uint2* items;  // x = fft << 2 | kind, y = tile index
+  int n_items;
+  unsigned* counters;  // [0] queue head, [1 + f] finished row items of f, [n_fft + 1] error word
+  const float2* tw;    // concatenated twiddle tables, cfg id -> offset in tw_off
+  int tw_off[kNumCfg];
+  int conj;            // 1: inverse transform
+  int n_fft;           // counters[n_fft + 1] is the error word
+};
+
+constexpr int kMaxSpins = 1 << 24;
+
+// One configuration's tile as its own (flattened) function, so that every
+// register array of the pass stays in registers inside the large dispatch.
+template <class K>
+__device__ __noinline__ __attribute__((flatten)) void tile(const PassArgs& pa, int w, float2* lds, TileIO io) {
+  static_assert(K::valid() && K::THREADS == kThreads, "batched configurations use 512 threads");
+  fft_tile<K, -1>(pa, w, lds, io);
+}
+
+__device__ __forceinline__ void run_tile(int cfg, const PassArgs& pa, int w, float2* lds, TileIO io) {
+  switch (cfg) {
+    case 1: tile<BR2>(pa, w, lds, io); break;
+    case 2: tile<BR4>(pa, w, lds, io); break;
+    case 3: tile<BR8>(pa, w, lds, io); break;
+    case 4: tile<BR16>(pa, w, lds, io); break;
+    case 5: tile<BR32>(pa, w, lds, io); break;
+    case 6: tile<BR64>(pa, w, lds, io); break;
+    case 7: tile<BR128>(pa, w, lds, io); break;
+    case 8: tile<BR256>(pa, w, lds, io); break;
+    case 9: tile<BR512>(pa, w, lds, io); break;
+    case 10: tile<BR1024>(pa, w, lds, io); break;
+    case 11: tile<BR2048>(pa, w, lds, io); break;
+    case 12: tile<BR4096>(pa, w, lds, io); break;
+    case 13: tile<BR8192>(pa, w, lds, io); break;
+    case 14: tile<BR16384>(pa, w, lds, io); break;
+    case 17: tile<BC2>(pa, w, lds, io); break;
+    case 18: tile<BC4>(pa, w, lds, io); break;
+    case 19: tile<BC8>(pa, w, lds, io); break;
+    case 20: tile<BC16>(pa, w, lds, io); break;
+    case 21: tile<BC32>(pa, w, lds, io); break;
+    case 22: tile<BC64>(pa, w, lds, io); break;
+    case 23: tile<BC128>(pa, w, lds, io); break;
+    case 24: tile<BC256>(pa, w, lds, io); break;
+    case 25: tile<BC512>(pa, w, lds, io); break;
+    case 26: tile<BC1024>(pa, w, lds, io); break;
+    case 27: tile<BC2048>(pa, w, lds, io); break;
+    case 28: tile<BC4096>(pa, w, lds, io); break;
+    case 29: tile<BC8192>(pa, w, lds, io); break;
+    case 30: tile<BC16384>(pa, w, lds, io); break;
+    default: break;
+  }
+}
+
+__global__ void clear_counters(unsigned* c, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) c[i] = 0u;
+}
+
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void batched_kernel(BatchArgs a) {
+  __shared__ float2 lds[kLdsElems];
+  __shared__ int s_item;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = (int)atomicAdd(&a.counters[0], 1u);
+    __syncthreads();
+    const int it = s_item;
+    __syncthreads();  // every lane has read s_item before lane 0 may overwrite it
+    if (it >= a.n_items) break;
+    const uint2 item = a.items[it];
+    const int f = (int)(item.x >> 2);
+    const int kind = (int)(item.x & 3u);
+    const BatchDesc d = a.desc[f];
+    const bool inv = a.conj != 0;
+    const float s = inv ? 1.0f / ((float)d.rows * (float)d.cols) : 1.0f;
+    TileIO io;
+    PassArgs pa{};
+    pa.m1 = 1;
+    pa.ncols = d.cols;
+    if (kind == kCopyItem) {
+      if (threadIdx.x == 0) {
+        float2 v = d.in[0];
+        if (inv) v.y = -v.y;
+        d.out[0] = make_float2(v.x * s, inv ? -v.y * s : v.y * s);
+      }
+      continue;
+    }
+    if (kind == kRowItem) {
+      pa.in = d.in;
+      pa.out = d.out;
+      pa.nvec = d.rows;
+      pa.tw = a.tw + a.tw_off[d.row_cfg];
+      io.conj_in = inv;
+      io.conj_out = inv && d.rows == 1;
+      io.scale = d.rows == 1 ? s : 1.0f;
+      run_tile(d.row_cfg, pa, (int)item.y, lds, io);
+      // publish: own stores complete, workgroup joined, then one release increment
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+      if (threadIdx.x == 0) __hip_atomic_fetch_add(&a.counters[1 + f], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      if (d.nrow_items > 0) {
+        // Bounded wait: the counter always completes (see the file comment); the
+        // bound only guarantees that every wave exits even if that were broken,
+        // in which case the error word is set and the item is skipped.
+        if (threadIdx.x == 0) {
+          int spins = 0;
+          s_item = 0;
+          while (__hip_atomic_load(&a.counters[1 + f], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) <
+                 (unsigned)d.nrow_items) {
+            __builtin_amdgcn_s_sleep(2);
+            if (++spins > kMaxSpins) {
+              atomicOr(&a.counters[a.n_fft + 1], 1u);
+              s_item = -1;
+              break;
+            }
+          }
+        }
+        __syncthreads();
+        const bool timed_out = s_item < 0;
+        __syncthreads();  // every lane has read the flag before lane 0 reuses s_item
+        if (timed_out) continue;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      }
+      pa.in = d.nrow_items > 0 ? d.out : d.in;
+      pa.out = d.out;
+      pa.nvec = d.cols;
+      pa.tw = a.tw + a.tw_off[d.col_cfg];
+      io.conj_in = inv && d.nrow_items == 0;
+      io.conj_out = inv;
+      io.scale = s;
+      run_tile(d.col_cfg, pa, (int)item.y, lds, io);
+    }
+    __syncthreads();  // the LDS of this item is free before the next item starts
+  }
+}
+
+// ---------------------------------------------------------------- host side
+template <class K>
+constexpr PassKernel bdesc() {
+  return meta<K>();
+}
+
+const PassKernel* cfg_table() {
+  static const PassKernel tab[kNumCfg] = {
+      PassKernel{},   bdesc<BR2>(),    bdesc<BR4>(),    bdesc<BR8>(),   bdesc<BR16>(),   bdesc<BR32>(),
+      bdesc<BR64>(),  bdesc<BR128>(),  bdesc<BR256>(),  bdesc<BR512>(), bdesc<BR1024>(), bdesc<BR2048>(),
+      bdesc<BR4096>(), bdesc<BR8192>(), bdesc<BR16384>(), PassKernel{},  PassKernel{},    bdesc<BC2>(),
+      bdesc<BC4>(),   bdesc<BC8>(),    bdesc<BC16>(),   bdesc<BC32>(),  bdesc<BC64>(),   bdesc<BC128>(),
+      bdesc<BC256>(), bdesc<BC512>(),  bdesc<BC1024>(), bdesc<BC2048>(), bdesc<BC4096>(), bdesc<BC8192>(),
+      bdesc<BC16384>(), PassKernel{},
+  };
+  return tab;
+}
+
+int ilog2i(int64_t n) {
+  int k = 0;
+  while ((int64_t(1) << k) < n) ++k;
+  return k;
+}
+
+}  // namespace
 
 struct BatchedPlan {
   int64_t count = 0;
+  std::vector<int32_t> rows, cols;
+  std::vector<int32_t> row_cfg, col_cfg, nrow, ncol;
+  int64_t total_points = 0;
+  double flops = 0;
+  int num_cu = 0;
+  // tuning choice
+  int grid_mult = 2;
+  int order = 1;
+  std::string tune_source = "default";
+  // device state
+  BatchDesc* d_desc = nullptr;
+  BatchDesc* h_desc = nullptr;  // pinned staging copy
+  uint2* d_items = nullptr;
+  int n_items = 0;
+  unsigned* d_counters = nullptr;
+  float2* d_tw = nullptr;
+  int tw_off[kNumCfg] = {};
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph[2] = {nullptr, nullptr};
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
+  hipEvent_t staged = nullptr;
+  bool staged_pending = false;
+  std::vector<const void*> last_in, last_out;
 };
 
-fft2d_status create_batched(int64_t, const int64_t*, const int64_t*, BatchedPlan** out, std::string* err) {
+namespace {
+
+// Item list for a given order policy. 0: every row item, then every column
+// item, transforms largest first. 1: transforms largest first, in chunks of
+// about 64 MiB of data; a chunk's row items, then the previous chunk's column
+// items (so column items mostly read data still in the MALL).
+std::vector<uint2> build_items(const BatchedPlan& bp, int order) {
+  std::vector<int> idx((size_t)bp.count);
+  for (int64_t i = 0; i < bp.count; ++i) idx[(size_t)i] = (int)i;
+  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
+    return (int64_t)bp.rows[a] * bp.cols[a] > (int64_t)bp.rows[b] * bp.cols[b];
+  });
+  auto rows_of = [&](int f, std::vector<uint2>& out) {
+    if (bp.rows[f] == 1 && bp.cols[f] == 1) {
+      out.push_back(make_uint2((unsigned)f << 2 | kCopyItem, 0));
+      return;
+    }
+    for (int t = 0; t < bp.nrow[f]; ++t) out.push_back(make_uint2((unsigned)f << 2 | kRowItem, (unsigned)t));
+  };
+  auto cols_of = [&](int f, std::vector<uint2>& out) {
+    for (int t = 0; t < bp.ncol[f]; ++t) out.push_back(make_uint2((unsigned)f << 2 | kColItem, (unsigned)t));
+  };
+  std::vector<uint2> items;
+  if (order == 0) {
+    for (int f : idx) rows_of(f, items);
+    for (int f : idx) cols_of(f, items);
+    return items;
+  }
+  const int64_t chunk_points = (int64_t(64) << 20) / 8;
+  std::vector<int> prev, cur;
+  int64_t acc = 0;
+  for (size_t k = 0; k < idx.size(); ++k) {
+    const int f = idx[k];
+    rows_of(f, items);
+    cur.push_back(f);
+    acc += (int64_t)bp.rows[f] * bp.cols[f];
+    if (acc >= chunk_points || k + 1 == idx.size()) {
+      for (int g : prev) cols_of(g, items);
+      prev.swap(cur);
+      cur.clear();
+      acc = 0;
+    }
+  }
+  for (int g : prev) cols_of(g, items);
+  return items;
+}
+
+hipError_t launch_batched(BatchedPlan* bp, int conj, int grid, hipStream_t s) {
+  const int nc = (int)bp->count + 2;
+  hipLaunchKernelGGL(clear_counters, dim3((unsigned)std::min(64, (nc + 255) / 256)), dim3(256), 0, s, bp->d_counters, nc);
+  BatchArgs a{};
+  a.desc = bp->d_desc;
+  a.items = bp->d_items;
+  a.n_items = bp->n_items;
+  a.counters = bp->d_counters;
+  a.tw = bp->d_tw;
+  for (int i = 0; i < kNumCfg; ++i) a.tw_off[i] = bp->tw_off[i];
+  a.conj = conj;
+  a.n_fft = (int)bp->count;
+  hipLaunchKernelGGL(batched_kernel, dim3((unsigned)grid), dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t upload_items(BatchedPlan* bp, const std::vector<uint2>& items) {
+  if (bp->d_items) (void)hipFree(bp->d_items);
+  bp->d_items = nullptr;
+  bp->n_items = (int)items.size();
+  hipError_t e = hipMalloc((void**)&bp->d_items, std::max<size_t>(1, items.size()) * sizeof(uint2));
+  if (e != hipSuccess) return e;
+  return hipMemcpy(bp->d_items, items.data(), items.size() * sizeof(uint2), hipMemcpyHostToDevice);
+}
+
+std::string shape_signature(const BatchedPlan& bp) {
+  std::map<std::pair<int, int>, int> hist;
+  for (int64_t i = 0; i < bp.count; ++i) hist[{bp.rows[i], bp.cols[i]}]++;
+  std::ostringstream os;
+  for (auto& kv : hist) os << kv.first.first << "x" << kv.first.second << "*" << kv.second << ";";
+  return os.str();
+}
+
+uint64_t fnv1a(const std::string& s) {
+  uint64_t h = 1469598103934665603ull;
+  for (unsigned char c : s) {
+    h ^= c;
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+std::string cache_path() {
+  const char* p = std::getenv("FFT2D_TUNE_CACHE");
+  if (p && *p) return p;
+  const char* home = std::getenv("HOME");
+  if (!home || !*home) return "";
+  return std::string(home) + "/.cache/fft2d_tune.txt";
+}
+
+// Cache lines: "<key hex> <grid_mult> <order>"; malformed lines are ignored.
+bool cache_lookup(const std::string& key, int* mult, int* order) {
+  const std::string path = cache_path();
+  if (path.empty()) return false;
+  std::ifstream in(path);
+  std::string line;
+  bool found = false;
+  while (std::getline(in, line)) {
+    std::istringstream ls(line);
+    std::string k;
+    int m = 0, o = -1;
+    if (!(ls >> k >> m >> o)) continue;
+    if (k == key && m >= 1 && m <= 8 && (o == 0 || o == 1)) {
+      *mult = m;
+      *order = o;
+      found = true;
+    }
+  }
+  return found;
+}
+
+void cache_store(const std::string& key, int mult, int order) {
+  const std::string path = cache_path();
+  if (path.empty()) return;
+  std::ofstream out(path, std::ios::app);
+  if (!out) {
+    const size_t slash = path.find_last_of('/');
+    if (slash == std::string::npos) return;
+    (void)::mkdir(path.substr(0, slash).c_str(), 0755);  // one level, best effort
+    out.open(path, std::ios::app);
+  }
+  if (out) out << key << " " << mult << " " << order << "\n";
+}
+
+// Time one candidate (grid multiplier, order) on scratch buffers; median of reps.
+float time_candidate(BatchedPlan* bp, int mult, int order, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  if (upload_items(bp, build_items(*bp, order)) != hipSuccess) return 1e30f;
+  std::vector<float> ts;
+  for (int r = 0; r < 4; ++r) {
+    (void)hipEventRecord(e0, s);
+    if (launch_batched(bp, 0, mult * bp->num_cu, s) != hipSuccess) return 1e30f;
+    (void)hipEventRecord(e1, s);
+    if (hipEventSynchronize(e1) != hipSuccess) return 1e30f;
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (r > 0) ts.push_back(ms);
+  }
+  std::sort(ts.begin(), ts.end());
+  return ts[ts.size() / 2];
+}
+
+}  // namespace
+
+fft2d_status create_batched(int64_t count, const int64_t* rows, const int64_t* cols, BatchedPlan** out,
+                            std::string* err) {
   *out = nullptr;
-  *err = "batched plans are not available in this build";
-  return FFT2D_ERR_WRONG_PLAN_KIND;
+  BatchedPlan* bp = new (std::nothrow) BatchedPlan();
+  if (!bp) {
+    *err = "host allocation failed";
+    return FFT2D_ERR_OUT_OF_MEMORY;
+  }
+  auto fail = [&](fft2d_status st, const std::string& msg) {
+    destroy_batched(bp);
+    *err = msg;
+    return st;
+  };
+  auto hipfail = [&](hipError_t e, const char* what) {
+    return fail(e == hipErrorOutOfMemory ? FFT2D_ERR_OUT_OF_MEMORY : FFT2D_ERR_HIP,
+                std::string(what) + ": " + hipGetErrorName(e));
+  };
+  bp->count = count;
+  const PassKernel* tab = cfg_table();
+  for (int64_t i = 0; i < count; ++i) {
+    const int M = (int)rows[i], N = (int)cols[i];
+    bp->rows.push_back(M);
+    bp->cols.push_back(N);
+    const int rc = N > 1 ? ilog2i(N) : 0;
+    const int cc = M > 1 ? 16 + ilog2i(M) : 0;
+    bp->row_cfg.push_back(rc);
+    bp->col_cfg.push_back(cc);
+    bp->nrow.push_back(N > 1 ? (M + tab[rc].C - 1) / tab[rc].C : 0);
+    bp->ncol.push_back(M > 1 ? (N + tab[cc].C - 1) / tab[cc].C : 0);
+    bp->total_points += (int64_t)M * N;
+    const double p = (double)M * N;
+    bp->flops += p > 1 ? 5.0 * p * std::log2(p) : 0.0;
+  }
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hipfail(e, "hipGetDevice");
+  e = hipDeviceGetAttribute(&bp->num_cu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return hipfail(e, "hipDeviceGetAttribute");
+  // twiddle tables of every configuration (all, so a pointer change never needs new tables)
+  {
+    std::vector<float2> host;
+    for (int c = 0; c < kNumCfg; ++c) {
+      bp->tw_off[c] = (int)host.size();
+      if (tab[c].L == 0) continue;
+      const size_t n = twiddle_count(tab[c]);
+      host.resize(host.size() + n);
+      if (n) fill_twiddles(tab[c], host.data() + bp->tw_off[c]);
+    }
+    if (host.empty()) host.push_back(make_float2(0.f, 0.f));
+    if ((e = hipMalloc((void**)&bp->d_tw, host.size() * sizeof(float2))) != hipSuccess) return hipfail(e, "twiddles");
+    if ((e = hipMemcpy(bp->d_tw, host.data(), host.size() * sizeof(float2), hipMemcpyHostToDevice)) != hipSuccess)
+      return hipfail(e, "twiddle upload");
+  }
+  if ((e = hipMalloc((void**)&bp->d_desc, (size_t)count * sizeof(BatchDesc))) != hipSuccess)
+    return hipfail(e, "descriptor table");
+  if ((e = hipHostMalloc((void**)&bp->h_desc, (size_t)count * sizeof(BatchDesc), hipHostMallocDefault)) != hipSuccess)
+    return hipfail(e, "pinned descriptor staging");
+  if ((e = hipMalloc((void**)&bp->d_counters, (size_t)(count + 2) * sizeof(unsigned))) != hipSuccess)
+    return hipfail(e, "counters");
+  if ((e = hipStreamCreateWithFlags(&bp->cap_stream, hipStreamNonBlocking)) != hipSuccess) return hipfail(e, "stream");
+  if ((e = hipEventCreateWithFlags(&bp->staged, hipEventDisableTiming)) != hipSuccess) return hipfail(e, "event");
+  for (int64_t i = 0; i < count; ++i) {
+    BatchDesc& d = bp->h_desc[i];
+    d.in = nullptr;
+    d.out = nullptr;
+    d.rows = bp->rows[(size_t)i];
+    d.cols = bp->cols[(size_t)i];
+    d.row_cfg = bp->row_cfg[(size_t)i];
+    d.col_cfg = bp->col_cfg[(size_t)i];
+    d.nrow_items = bp->nrow[(size_t)i];
+    d.pad = 0;
+  }
+
+  // Autotuner: persistent grid size (workgroups per CU) and item order,
+  // measured on scratch buffers of this plan's shapes, cached per shape set.
+  const char* tune_env = std::getenv("FFT2D_TUNE");
+  const std::string mode = tune_env ? tune_env : "cached";
+  std::ostringstream keys;
+  keys << "gfx950|v1|" << shape_signature(*bp);
+  char keyhex[32];
+  std::snprintf(keyhex, sizeof(keyhex), "%016llx", (unsigned long long)fnv1a(keys.str()));
+  bool have = false;
+  if (mode == "off") {
+    have = true;
+    bp->tune_source = "default";
+  } else if (mode != "full" && cache_lookup(keyhex, &bp->grid_mult, &bp->order)) {
+    have = true;
+    bp->tune_source = "cache";
+  }
+  if (!have) {
+    float2 *sin = nullptr, *sout = nullptr;
+    const size_t bytes = (size_t)bp->total_points * sizeof(float2);
+    if ((e = hipMalloc((void**)&sin, bytes)) != hipSuccess) return hipfail(e, "tuning buffers");
+    if ((e = hipMalloc((void**)&sout, bytes)) != hipSuccess) {
+      (void)hipFree(sin);
+      return hipfail(e, "tuning buffers");
+    }
+    (void)hipMemsetAsync(sin, 0, bytes, bp->cap_stream);
+    int64_t off = 0;
+    for (int64_t i = 0; i < count; ++i) {
+      bp->h_desc[i].in = sin + off;
+      bp->h_desc[i].out = sout + off;
+      off += (int64_t)bp->rows[(size_t)i] * bp->cols[(size_t)i];
+    }
+    e = hipMemcpyAsync(bp->d_desc, bp->h_desc, (size_t)count * sizeof(BatchDesc), hipMemcpyHostToDevice,
+                       bp->cap_stream);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    float best = 1e30f;
+    if (e == hipSuccess) {
+      const int mults[] = {1, 2, 3};
+      for (int m : mults)
+        for (int o = 0; o < 2; ++o) {
+          const float t = time_candidate(bp, m, o, bp->cap_stream, e0, e1);
+          if (t < best) {
+            best = t;
+            bp->grid_mult = m;
+            bp->order = o;
+          }
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(bp->cap_stream);
+    (void)hipFree(sin);
+    (void)hipFree(sout);
+    for (int64_t i = 0; i < count; ++i) bp->h_desc[i].in = bp->h_desc[i].out = nullptr;
+    if (e != hipSuccess) return hipfail(e, "autotune");
+    if (best >= 1e29f) return fail(FFT2D_ERR_HIP, "autotune: every candidate failed");
+    bp->tune_source = "tuned";
+    cache_store(keyhex, bp->grid_mult, bp->order);
+  }
+  if ((e = upload_items(bp, build_items(*bp, bp->order))) != hipSuccess) return hipfail(e, "item table");
+
+  // One graph per direction: counter clear (a kernel, no memset node) + the persistent kernel.
+  for (int dir = 0; dir < 2; ++dir) {
+    if ((e = hipStreamBeginCapture(bp->cap_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+      return hipfail(e, "graph capture");
+    hipError_t le = launch_batched(bp, dir, bp->grid_mult * bp->num_cu, bp->cap_stream);
+    e = hipStreamEndCapture(bp->cap_stream, &bp->graph[dir]);
+    if (le != hipSuccess) return hipfail(le, "graph capture launch");
+    if (e != hipSuccess) return hipfail(e, "graph capture end");
+    if ((e = hipGraphInstantiate(&bp->exec[dir], bp->graph[dir], nullptr, nullptr, 0)) != hipSuccess)
+      return hipfail(e, "graph instantiate");
+  }
+  *out = bp;
+  return FFT2D_OK;
 }
 
-fft2d_status exec_batched(BatchedPlan*, const void* const*, void* const*, int, hipStream_t, std::string* err) {
-  *err = "batched plans are not available in this build";
-  return FFT2D_ERR_WRONG_PLAN_KIND;
+fft2d_status exec_batched(BatchedPlan* bp, const void* const* in, void* const* out, int direction, hipStream_t s,
+                          std::string* err) {
+  bool changed = bp->last_in.size() != (size_t)bp->count;
+  for (int64_t i = 0; i < bp->count; ++i) {
+    if (!in[i] || !out[i]) {
+      *err = "pointer " + std::to_string(i) + " is NULL";
+      return FFT2D_ERR_NULL_POINTER;
+    }
+    if ((reinterpret_cast<uintptr_t>(in[i]) & 7) || (reinterpret_cast<uintptr_t>(out[i]) & 7)) {
+      *err = "pointer " + std::to_string(i) + " is not 8-byte aligned";
+      return FFT2D_ERR_MISALIGNED;
+    }
+    const uintptr_t a = reinterpret_cast<uintptr_t>(in[i]), b = reinterpret_cast<uintptr_t>(out[i]);
+    const uintptr_t bytes = (uintptr_t)bp->rows[(size_t)i] * bp->cols[(size_t)i] * 8;
+    if (a != b && a < b + bytes && b < a + bytes) {
+      *err = "input and output " + std::to_string(i) + " overlap without being identical";
+      return FFT2D_ERR_OVERLAP;
+    }
+    if (!changed && (bp->last_in[(size_t)i] != in[i] || bp->last_out[(size_t)i] != out[i])) changed = true;
+  }
+  hipError_t e;
+  if (changed) {
+    // the staging copy may still be read by the previous upload
+    if (bp->staged_pending && (e = hipEventSynchronize(bp->staged)) != hipSuccess) {
+      *err = std::string("staging wait: ") + hipGetErrorName(e);
+      return FFT2D_ERR_HIP;
+    }
+    for (int64_t i = 0; i < bp->count; ++i) {
+      bp->h_desc[i].in = (const float2*)in[i];
+      bp->h_desc[i].out = (float2*)out[i];
+    }
+    e = hipMemcpyAsync(bp->d_desc, bp->h_desc, (size_t)bp->count * sizeof(BatchDesc), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipEventRecord(bp->staged, s);
+    if (e != hipSuccess) {
+      *err = std::string("descriptor upload: ") + hipGetErrorName(e);
+      return FFT2D_ERR_HIP;
+    }
+    bp->staged_pending = true;
+    bp->last_in.assign(in, in + bp->count);
+    bp->last_out.assign(out, out + bp->count);
+  }
+  e = hipGraphLaunch(bp->exec[direction == FFT2D_INVERSE ? 1 : 0], s);
+  if (e != hipSuccess) {
+    *err = std::string("graph launch: ") + hipGetErrorName(e);
+    return FFT2D_ERR_HIP;
+  }
+  return FFT2D_OK;
 }
 
-void destroy_batched(BatchedPlan* bp) { delete bp; }
+void destroy_batched(BatchedPlan* bp) {
+  if (!bp) return;
+  for (int d = 0; d < 2; ++d) {
+    if (bp->exec[d]) (void)hipGraphExecDestroy(bp->exec[d]);
+    if (bp->graph[d]) (void)hipGraphDestroy(bp->graph[d]);
+  }
+  if (bp->staged) {
+    (void)hipEventSynchronize(bp->staged);
+    (void)hipEventDestroy(bp->staged);
+  }
+  if (bp->cap_stream) (void)hipStreamDestroy(bp->cap_stream);
+  if (bp->d_desc) (void)hipFree(bp->d_desc);
+  if (bp->h_desc) (void)hipHostFree(bp->h_desc);
+  if (bp->d_items) (void)hipFree(bp->d_items);
+  if (bp->d_counters) (void)hipFree(bp->d_counters);
+  if (bp->d_tw) (void)hipFree(bp->d_tw);
+  delete bp;
+}
 
-std::string describe_batched(const BatchedPlan*) { return "batched"; }
+std::string describe_batched(const BatchedPlan* bp) {
+  std::ostringstream os;
+  os << "batched count=" << bp->count << " points=" << bp->total_points << " items=" << bp->n_items
+     << " grid=" << bp->grid_mult << "x" << bp->num_cu << " order=" << (bp->order ? "chunked" : "rows-then-columns")
+     << " tune=" << bp->tune_source << " threads=" << kThreads << " lds=" << kLdsElems * 8;
+  return os.str();
+}
 
 }  // namespace fft2d

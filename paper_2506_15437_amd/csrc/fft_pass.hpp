@@ -314,14 +314,21 @@ __device__ __forceinline__ void run_pass(float2 (&d)[K::E], float2* lds, int tt,
   }
 }
 
-template <class K, int DIR, bool NT = false, int WPE = 1, int SB = 0>
-__global__ __launch_bounds__(K::THREADS) __attribute__((amdgpu_waves_per_eu(WPE))) void pass_kernel(PassArgs a) {
-  static_assert(K::valid(), "invalid pass configuration");
-  __shared__ float2 lds[K::LDS_ELEMS];
+// Conjugation and scaling of one tile's input and output. A forward-sign
+// kernel computes the inverse transform as conj(F(conj(x))) / (M N); the
+// batched path uses this instead of a second set of kernels.
+struct TileIO {
+  bool conj_in = false;
+  bool conj_out = false;
+  float scale = 1.0f;
+};
+
+// One workgroup's tile of a pass: C vectors starting at vector w*C.
+template <class K, int DIR, bool NT = false, int SB = 0>
+__device__ __forceinline__ void fft_tile(const PassArgs& a, int w, float2* lds, TileIO io) {
   const int t = threadIdx.x;
   const int c = K::COL ? (t % K::C) : (t / K::T);
   const int tt = K::COL ? (t / K::C) : (t % K::T);
-  const int w = K::COL ? xcd_remap(blockIdx.x, a.nblocks) : (int)blockIdx.x;
   const int64_t v = (int64_t)w * K::C + c;
   const bool active = v < a.nvec;
   int64_t base_in, base_out, es_in, es_out;
@@ -348,17 +355,29 @@ __global__ __launch_bounds__(K::THREADS) __attribute__((amdgpu_waves_per_eu(WPE)
       constexpr int j = decltype(J)::value;
       d[j] = gload<NT>(a.in + base_in + (int64_t)(tt + K::T * j) * es_in);
     });
+    if (io.conj_in) static_for<0, K::E>([&](auto J) { d[decltype(J)::value].y = -d[decltype(J)::value].y; });
   } else {
     static_for<0, K::E>([&](auto J) { d[decltype(J)::value] = make_float2(0.f, 0.f); });
   }
   static_for<0, K::P>([&](auto Pp) { run_pass<K, DIR, decltype(Pp)::value, SB>(d, lds, tt, c, a.tw); });
   if (active) {
-    const float sc = a.scale;
+    const float sc = io.scale;
+    const float sy = io.conj_out ? -sc : sc;
     static_for<0, K::E>([&](auto J) {
       constexpr int j = decltype(J)::value;
-      gstore<NT>(a.out + base_out + (int64_t)(tt + K::T * j) * es_out, make_float2(d[j].x * sc, d[j].y * sc));
+      gstore<NT>(a.out + base_out + (int64_t)(tt + K::T * j) * es_out, make_float2(d[j].x * sc, d[j].y * sy));
     });
   }
+}
+
+template <class K, int DIR, bool NT = false, int WPE = 1, int SB = 0>
+__global__ __launch_bounds__(K::THREADS) __attribute__((amdgpu_waves_per_eu(WPE))) void pass_kernel(PassArgs a) {
+  static_assert(K::valid(), "invalid pass configuration");
+  __shared__ float2 lds[K::LDS_ELEMS];
+  const int w = K::COL ? xcd_remap(blockIdx.x, a.nblocks) : (int)blockIdx.x;
+  TileIO io;
+  io.scale = a.scale;
+  fft_tile<K, DIR, NT, SB>(a, w, lds, io);
 }
 
 // Row pass with combine (first half of a split column transform, see
@@ -434,6 +453,24 @@ hipError_t launch_rowc(const PassArgs& a, int dir, hipStream_t s) {
   if (dir < 0) hipLaunchKernelGGL((rowc_kernel<K, -1, WPE>), dim3(a.nblocks), dim3(K::THREADS), 0, s, a);
   else hipLaunchKernelGGL((rowc_kernel<K, +1, WPE>), dim3(a.nblocks), dim3(K::THREADS), 0, s, a);
   return hipGetLastError();
+}
+
+// Shape metadata of a configuration (no kernel instantiated).
+template <class K>
+constexpr PassKernel meta() {
+  PassKernel k{};
+  k.L = K::L;
+  k.E = K::E;
+  k.T = K::T;
+  k.C = K::C;
+  k.Q = K::Q;
+  k.threads = K::THREADS;
+  k.colmode = K::COL ? 1 : 0;
+  k.npass = K::P;
+  for (int p = 0; p < kMaxPasses; ++p) k.radix[p] = p < K::P ? K::radix(p) : 0;
+  k.lds_bytes = (size_t)K::LDS_ELEMS * 8;
+  k.launch = nullptr;
+  return k;
 }
 
 // WPE: minimum waves per SIMD the compiler must allow (bounds VGPR use).

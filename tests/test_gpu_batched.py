@@ -1,0 +1,148 @@
+"""GPU parity of the batched path: many shapes, one persistent launch, HIP graph."""
+
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_util import TOL, dev, host, rel_l2, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def F():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2506_15437_amd as F
+    return F
+
+
+@pytest.fixture(autouse=True)
+def _tune_cache(tmp_path, monkeypatch):
+    monkeypatch.setenv("FFT2D_TUNE_CACHE", str(tmp_path / "tune.txt"))
+
+
+# every length 1 ... 2048 appears as rows and as cols, plus degenerate 1 x 1
+MIXED = [(1, 1), (1, 2), (2, 1), (4, 8), (8, 4), (16, 32), (32, 16), (64, 64), (1, 512), (512, 1), (128, 256),
+         (256, 128), (1024, 16), (16, 1024), (2048, 8), (8, 2048), (64, 2048), (2048, 64), (512, 512), (2, 4096),
+         (4096, 2), (16384, 1), (1, 16384), (8192, 4), (4, 8192), (16384, 2)]
+
+
+def _run(F, plan, xs, direction, outs=None):
+    ins = [dev(x) for x in xs]
+    res = plan(ins, direction, outs)
+    return ins, res
+
+
+@pytest.mark.parametrize("tune", ["off", "full"])
+def test_batched_mixed_shapes(F, tune, monkeypatch):
+    monkeypatch.setenv("FFT2D_TUNE", tune)
+    say("case batched mixed shapes tune=%s" % tune)
+    xs = synth.batched_grids(11, MIXED)
+    plan = F.BatchedPlan(MIXED)
+    try:
+        say(plan.describe())
+        _, ys = _run(F, plan, xs, F.FORWARD)
+        _, zs = _run(F, plan, xs, F.INVERSE)
+        worst_f = worst_i = 0.0
+        for x, y, z, s in zip(xs, ys, zs, MIXED):
+            ef = rel_l2(host(y), oracle.fft2_forward(x))
+            ei = rel_l2(host(z), oracle.ifft2(x))
+            worst_f, worst_i = max(worst_f, ef), max(worst_i, ei)
+            assert ef <= TOL and ei <= TOL, (s, ef, ei)
+        say("batched mixed worst rel_l2 fwd=%.3e inv=%.3e" % (worst_f, worst_i))
+    finally:
+        plan.close()
+
+
+def test_batched_replay_pointer_change_and_in_place(F, monkeypatch):
+    import torch
+    monkeypatch.setenv("FFT2D_TUNE", "off")
+    shapes = [(64, 128), (256, 64), (32, 32), (1024, 256)]
+    say("case batched replay / pointer change")
+    xs = synth.batched_grids(12, shapes)
+    plan = F.BatchedPlan(shapes)
+    try:
+        ins = [dev(x) for x in xs]
+        a = plan(ins, F.FORWARD)
+        b = plan(ins, F.FORWARD)  # graph replay, same pointers
+        torch.cuda.synchronize()
+        for u, v in zip(a, b):
+            assert torch.equal(u, v)
+        outs = [torch.empty_like(t) for t in ins]  # new output pointers
+        c = plan(ins, F.FORWARD, outs)
+        torch.cuda.synchronize()
+        for u, v in zip(a, c):
+            assert torch.equal(u, v)
+        inplace = [t.clone() for t in ins]
+        plan(inplace, F.FORWARD, inplace)
+        for u, v in zip(a, inplace):
+            assert torch.equal(u, v)
+        for x, u in zip(xs, a):
+            assert rel_l2(host(u), oracle.fft2_forward(x)) <= TOL
+    finally:
+        plan.close()
+
+
+def test_batched_rejects_bad_input(F, monkeypatch):
+    import torch
+    monkeypatch.setenv("FFT2D_TUNE", "off")
+    plan = F.BatchedPlan([(8, 8), (16, 16)])
+    try:
+        a = torch.zeros(8, 8, dtype=torch.complex64, device="cuda")
+        b = torch.zeros(16, 16, dtype=torch.complex64, device="cuda")
+        with pytest.raises(F.Fft2dError) as e:
+            F.fft2d_exec_batched(plan.handle, [a.data_ptr(), b.data_ptr() + 4], [a.data_ptr(), b.data_ptr()], -1, 0)
+        assert e.value.status == 4
+        with pytest.raises(F.Fft2dError) as e:
+            F.fft2d_exec_batched(plan.handle, [a.data_ptr(), b.data_ptr()], [a.data_ptr(), b.data_ptr() + 8], -1, 0)
+        assert e.value.status == 9
+        with pytest.raises(F.Fft2dError) as e:
+            F.fft2d_exec(plan.handle, a.data_ptr(), a.data_ptr(), -1, 0)
+        assert e.value.status == 5
+        with pytest.raises(ValueError):
+            plan([a], F.FORWARD)
+    finally:
+        plan.close()
+
+
+def test_batched_512_uneven_shapes(F):
+    """512 transforms of 2^a x 2^b, a, b in [6, 11] drawn from seed 4, one persistent launch.
+
+    Every output is checked against the plain path (fft2d_exec of the same shape)
+    on the GPU, a sample of 24 against the FP64 oracle, and all against Parseval."""
+    import torch
+    shapes = synth.pow2_shapes(4, 512)
+    say("case batched 512 shapes, %d points" % sum(r * c for r, c in shapes))
+    xs = synth.batched_grids(4, shapes)
+    plan = F.BatchedPlan(shapes)
+    try:
+        say(plan.describe())
+        ins = [dev(x) for x in xs]
+        ys = plan(ins, F.FORWARD)
+        torch.cuda.synchronize()
+        worst_plain = 0.0
+        for x_d, y in zip(ins, ys):
+            ref = F.fft2(x_d)
+            e = float(torch.linalg.vector_norm(y - ref) / torch.linalg.vector_norm(ref))
+            worst_plain = max(worst_plain, e)
+            # Parseval: sum |Y|^2 = M N sum |x|^2
+            m, n = x_d.shape
+            lhs = float(torch.sum(torch.abs(y.to(torch.complex128)) ** 2))
+            rhs = m * n * float(torch.sum(torch.abs(x_d.to(torch.complex128)) ** 2))
+            assert abs(lhs - rhs) <= 1e-5 * rhs
+        say("batched 512 vs plain path worst rel_l2=%.3e" % worst_plain)
+        assert worst_plain <= 2 * TOL
+        rng = np.random.default_rng(0)
+        worst = 0.0
+        for i in rng.choice(len(shapes), size=24, replace=False):
+            e = rel_l2(host(ys[i]), oracle.fft2_forward(xs[i]))
+            worst = max(worst, e)
+            assert e <= TOL, (i, shapes[i], e)
+        say("batched 512 sample vs oracle worst rel_l2=%.3e" % worst)
+    finally:
+        plan.close()
