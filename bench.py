@@ -111,6 +111,57 @@ def time_backward(F, torch, batch, rows, cols, steps, warmup, seed):
             "backward_over_plain": bwd / fwd, "plain_gflops": fl / fwd / 1e6, "backward_gflops": fl / bwd / 1e6}
 
 
+def time_batched(F, torch, steps, warmup, seed):
+    """512 transforms of 2^a x 2^b (a, b in [6, 11] from `seed`): one graph replay of the
+    persistent kernel against 512 fft2d_exec calls (two kernel launches each) on one stream."""
+    import synth
+    shapes = synth.pow2_shapes(seed, 512)
+    xs = [torch.from_numpy(x).to("cuda") for x in synth.batched_grids(seed, shapes)]
+    ys = [torch.empty_like(x) for x in xs]
+    zs = [torch.empty_like(x) for x in xs]
+    plan = F.BatchedPlan(shapes)
+    stream = torch.cuda.current_stream()
+    sh = int(stream.cuda_stream)
+    iptr = [x.data_ptr() for x in xs]
+    optr = [y.data_ptr() for y in ys]
+    plans = [F.get_plan(1, r, c, xs[0].device) for r, c in shapes]
+    zptr = [z.data_ptr() for z in zs]
+
+    def batched():
+        plan.exec_ptrs(iptr, optr, F.FORWARD, sh)
+
+    def plain():
+        for p, a, b in zip(plans, iptr, zptr):
+            F.fft2d_exec(p.handle, a, b, F.FORWARD, sh)
+
+    def run(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(steps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / steps
+
+    t_b = run(batched)
+    t_p = run(plain)
+    num = sum(float(torch.linalg.vector_norm(y - z)) ** 2 for y, z in zip(ys, zs)) ** 0.5
+    den = sum(float(torch.linalg.vector_norm(z)) ** 2 for z in zs) ** 0.5
+    points = sum(r * c for r, c in shapes)
+    fl = sum(flops_2d(r, c) for r, c in shapes)
+    res = {"workload": "512 forward 2D FFTs of 2^a x 2^b, a, b in [6, 11] from seed %d, %d points" % (seed, points),
+           "batched_ms": t_b, "plain_512_launches_ms": t_p, "speedup": t_p / t_b,
+           "batched_gflops": fl / t_b / 1e6, "plain_gflops": fl / t_p / 1e6,
+           "batched_hbm_gbps": 32.0 * points / t_b / 1e6,
+           "batched_vs_plain_rel_l2": num / den, "plan": plan.describe()}
+    plan.close()
+    return res
+
+
 def cpu_baseline(rows, cols, x, budget_s, max_reps):
     """The FP64 oracle (plain recursive radix-2, OpenMP) on the same input."""
     import oracle
@@ -140,6 +191,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work for the CPU baseline")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline (profiling runs)")
     ap.add_argument("--no-extras", action="store_true", help="skip the backward and batched comparisons")
+    ap.add_argument("--copy-only", action="store_true",
+                    help="only run plain device copies of the 4096x4096 grid (calibrates rocprofv3 byte counters)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -155,6 +208,15 @@ def main():
     import paper_2506_15437_amd as F
 
     rows = cols = 4096
+    if args.copy_only:
+        x = torch.empty((rows, cols), dtype=torch.complex64, device="cuda")
+        y = torch.empty_like(x)
+        x.zero_()
+        for _ in range(args.warmup + args.steps):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_only": True, "bytes_per_copy": 2 * x.numel() * 8, "copies": args.warmup + args.steps}))
+        return
     log("bench: %dx%d forward+inverse, steps=%d warmup=%d" % (rows, cols, args.steps, args.warmup))
     r = time_plain(F, torch, rows, cols, args.steps, args.warmup, args.seed)
     ms_per_step = r["wall"] / args.steps * 1e3
@@ -197,6 +259,8 @@ def main():
     if not args.no_extras:
         log("bench: backward vs plain, 8 x 2048 x 2048")
         result["backward_vs_plain"] = time_backward(F, torch, 8, 2048, 2048, 20, 3, 5)
+        log("bench: batched 512 shapes vs 512 plain launches")
+        result["batched_vs_plain"] = time_batched(F, torch, 10, 3, 4)
 
     if not args.no_cpu:
         log("bench: CPU baseline (FP64 oracle)")
