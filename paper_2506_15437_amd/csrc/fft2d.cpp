@@ -161,6 +161,8 @@ fft2d_status run_uniform(const fft2d_plan_s* p, const float2* in, float2* out, i
       a.in = in;
       a.out = p->work;
       a.tw = p->tw_row;
+      a.tw_count = (int64_t)twiddle_count(*p->row_k);
+      a.total = npts;
       a.twc = p->tw_comb;
       a.nvec = p->batch * p->rows;
       a.ncols = p->cols;
@@ -176,6 +178,8 @@ fft2d_status run_uniform(const fft2d_plan_s* p, const float2* in, float2* out, i
       a.in = p->work;
       a.out = out;
       a.tw = p->tw_col;
+      a.tw_count = (int64_t)twiddle_count(*p->col_k);
+      a.total = npts;
       a.nvec = p->batch * p->m1 * p->cols;
       a.ncols = p->cols;
       a.m1 = p->m1;
@@ -193,6 +197,8 @@ fft2d_status run_uniform(const fft2d_plan_s* p, const float2* in, float2* out, i
     a.in = src;
     a.out = out;
     a.tw = p->tw_row;
+    a.tw_count = (int64_t)twiddle_count(*p->row_k);
+    a.total = npts;
     a.nvec = p->batch * p->rows;
     a.ncols = p->cols;
     a.m1 = 1;
@@ -207,6 +213,8 @@ fft2d_status run_uniform(const fft2d_plan_s* p, const float2* in, float2* out, i
     a.in = src;
     a.out = out;
     a.tw = p->tw_col;
+    a.tw_count = (int64_t)twiddle_count(*p->col_k);
+    a.total = npts;
     a.nvec = p->batch * p->cols;
     a.ncols = p->cols;
     a.m1 = 1;

@@ -104,6 +104,7 @@ struct BatchArgs {
   unsigned* counters;  // [0] queue head, [1 + f] finished row items of f, [n_fft + 1] error word
   const float2* tw;    // concatenated twiddle tables, cfg id -> offset in tw_off
   int tw_off[kNumCfg];
+  int tw_cnt[kNumCfg];
   int conj;            // 1: inverse transform
   int n_fft;           // counters[n_fft + 1] is the error word
 };
@@ -162,7 +163,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
   for (;;) {
     if (threadIdx.x == 0) s_item = (int)atomicAdd(&a.counters[0], 1u);
     __syncthreads();
-    const int it = s_item;
+    const int it = __builtin_amdgcn_readfirstlane(s_item);
     __syncthreads();  // every lane has read s_item before lane 0 may overwrite it
     if (it >= a.n_items) break;
     const uint2 item = a.items[it];
@@ -175,6 +176,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
     PassArgs pa{};
     pa.m1 = 1;
     pa.ncols = d.cols;
+    pa.total = (int64_t)d.rows * d.cols;
     if (kind == kCopyItem) {
       if (threadIdx.x == 0) {
         float2 v = d.in[0];
@@ -188,6 +190,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
       pa.out = d.out;
       pa.nvec = d.rows;
       pa.tw = a.tw + a.tw_off[d.row_cfg];
+      pa.tw_count = a.tw_cnt[d.row_cfg];
       io.conj_in = inv;
       io.conj_out = inv && d.rows == 1;
       io.scale = d.rows == 1 ? s : 1.0f;
@@ -224,6 +227,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
       pa.out = d.out;
       pa.nvec = d.cols;
       pa.tw = a.tw + a.tw_off[d.col_cfg];
+      pa.tw_count = a.tw_cnt[d.col_cfg];
       io.conj_in = inv && d.nrow_items == 0;
       io.conj_out = inv;
       io.scale = s;
@@ -342,7 +346,11 @@ hipError_t launch_batched(BatchedPlan* bp, int conj, int grid, hipStream_t s) {
   a.n_items = bp->n_items;
   a.counters = bp->d_counters;
   a.tw = bp->d_tw;
-  for (int i = 0; i < kNumCfg; ++i) a.tw_off[i] = bp->tw_off[i];
+  const PassKernel* tab = cfg_table();
+  for (int i = 0; i < kNumCfg; ++i) {
+    a.tw_off[i] = bp->tw_off[i];
+    a.tw_cnt[i] = tab[i].L ? (int)twiddle_count(tab[i]) : 0;
+  }
   a.conj = conj;
   a.n_fft = (int)bp->count;
   hipLaunchKernelGGL(batched_kernel, dim3((unsigned)grid), dim3(kThreads), 0, s, a);

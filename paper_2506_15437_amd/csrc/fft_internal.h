@@ -26,7 +26,9 @@ struct PassArgs {
   const float2* in;
   float2* out;
   const float2* tw;   // inter-pass twiddle table of this pass kernel's schedule
+  int64_t tw_count;   // entries of tw
   const float2* twc;  // row pass with combine: W_M^j for j < M
+  int64_t total;      // points in the in and out buffers (bounds of every access)
   int64_t nvec;       // number of vectors
   int64_t ncols;      // column mode: points per row (N); unused in row mode
   int64_t m1;         // column mode: M1 of a split transform (1 = plain)

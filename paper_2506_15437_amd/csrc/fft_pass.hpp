@@ -134,6 +134,35 @@ __device__ __forceinline__ void gstore(float2* p, float2 v) {
   }
 }
 
+// Raw buffer access: a wave-uniform resource (base address and size in bytes)
+// plus a per-lane byte offset and a uniform byte offset. Accesses at or past
+// `bytes` read zero and drop stores (hardware range check).
+constexpr int kBufferDword3 = 0x00020000;
+constexpr int kAuxNontemporal = 2;
+
+struct Buf {
+  __amdgpu_buffer_rsrc_t r;
+  __device__ __forceinline__ Buf(const void* base, uint32_t bytes)
+      : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, kBufferDword3)) {}
+  template <int AUX = 0>
+  __device__ __forceinline__ float2 load(uint32_t voff, uint32_t soff) const {
+    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, AUX));
+  }
+  __device__ __forceinline__ void store(float2 v, uint32_t voff, uint32_t soff) const {
+    using raw = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(raw, v), r, (int)voff, (int)soff, 0);
+  }
+};
+
+// Byte size of the range [base_point, total_points) of a complex64 buffer, as
+// a buffer resource size (every tile's accesses lie below 2^28 points).
+__device__ __forceinline__ uint32_t span_bytes(int64_t total_points, int64_t base_point) {
+  int64_t n = total_points - base_point;
+  if (n < 0) n = 0;
+  if (n > (int64_t(1) << 28)) n = int64_t(1) << 28;
+  return (uint32_t)(n * 8);
+}
+
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
@@ -229,6 +258,10 @@ struct Cfg {
     if constexpr (COL) return pad(e) * C + c;
     else return c * ROWSTRIDE + pad(e);
   }
+  // Slot distance of point e0 + x from point e0 when the low four bits of e0
+  // and of x never carry into bit 4 (then pad(e0 + x) = pad(e0) + pad(x)), so
+  // that an address is a per-thread base plus a compile-time offset.
+  static constexpr int lds_delta(int x) { return COL ? pad(x) * C : pad(x); }
 
   static constexpr bool valid() {
     int prod = 1;
@@ -256,8 +289,9 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
 }
 
 // One pass: butterflies of this thread, then (unless last) the LDS exchange.
+// `tw` covers this pass kernel's twiddle table.
 template <class K, int DIR, int p, int SB = 0>
-__device__ __forceinline__ void run_pass(float2 (&d)[K::E], float2* lds, int tt, int c, const float2* __restrict__ tw) {
+__device__ __forceinline__ void run_pass(float2 (&d)[K::E], float2* lds, int tt, int c, const Buf& tw) {
   constexpr int R = K::radix(p);
   constexpr int Ns = K::ns(p);
   constexpr int NB = K::E / R;
@@ -272,10 +306,10 @@ __device__ __forceinline__ void run_pass(float2 (&d)[K::E], float2* lds, int tt,
       x[r] = d[i + NB * r];
     });
     if constexpr (p > 0) {
-      const float2* twp = tw + K::tw_off(p) + (b & (Ns - 1));
+      const uint32_t voff = (uint32_t)(b & (Ns - 1)) * 8u;
       static_for<1, R>([&](auto Rr) {
         constexpr int r = decltype(Rr)::value;
-        float2 w = twp[(r - 1) * Ns];
+        float2 w = tw.load(voff, (uint32_t)(K::tw_off(p) + (r - 1) * Ns) * 8u);
         if constexpr (DIR > 0) w.y = -w.y;
         x[r] = cmul(x[r], w);
       });
@@ -293,21 +327,33 @@ __device__ __forceinline__ void run_pass(float2 (&d)[K::E], float2* lds, int tt,
   if constexpr (!last) {
     constexpr int NBQ = NB / K::Q;
     constexpr int EQ = K::E / K::Q;
+    // reads: point tt + T j' (j' < EQ) of the round, tt < T, so the slot is
+    // lds_index(c, tt) + lds_delta(T j')
+    const int rbase = K::lds_index(c, tt);
     static_for<0, K::Q>([&](auto H) {
       constexpr int h = decltype(H)::value;
       static_for<0, NBQ>([&](auto I) {
         constexpr int i = h * NBQ + decltype(I)::value;
         const int b = tt + K::T * i;
         const int dst = (b / Ns) * Ns * R + (b & (Ns - 1)) - h * K::LQ;
-        static_for<0, R>([&](auto S) {
-          constexpr int s = decltype(S)::value;
-          lds[K::lds_index(c, dst + s * Ns)] = o[i * R + s];
-        });
+        if constexpr (Ns * R >= 16) {
+          // dst's low four bits are b mod Ns (< Ns), and s Ns adds multiples of Ns
+          const int wbase = K::lds_index(c, dst);
+          static_for<0, R>([&](auto S) {
+            constexpr int s = decltype(S)::value;
+            lds[wbase + K::lds_delta(s * Ns)] = o[i * R + s];
+          });
+        } else {
+          static_for<0, R>([&](auto S) {
+            constexpr int s = decltype(S)::value;
+            lds[K::lds_index(c, dst + s * Ns)] = o[i * R + s];
+          });
+        }
       });
       __syncthreads();
       static_for<0, EQ>([&](auto J) {
-        constexpr int j = h * EQ + decltype(J)::value;
-        d[j] = lds[K::lds_index(c, tt + K::T * j - h * K::LQ)];
+        constexpr int jj = decltype(J)::value;
+        d[h * EQ + jj] = lds[rbase + K::lds_delta(K::T * jj)];
       });
       __syncthreads();
     });
@@ -323,49 +369,68 @@ struct TileIO {
   float scale = 1.0f;
 };
 
-// One workgroup's tile of a pass: C vectors starting at vector w*C.
+// One workgroup's tile of a pass: C vectors starting at vector w*C (w must be
+// wave-uniform). Global memory is reached through buffer resources based at
+// the tile's first point, so every lane needs one 32-bit offset register and
+// the E points differ by uniform offsets.
 template <class K, int DIR, bool NT = false, int SB = 0>
 __device__ __forceinline__ void fft_tile(const PassArgs& a, int w, float2* lds, TileIO io) {
   const int t = threadIdx.x;
   const int c = K::COL ? (t % K::C) : (t / K::T);
   const int tt = K::COL ? (t / K::C) : (t % K::T);
-  const int64_t v = (int64_t)w * K::C + c;
-  const bool active = v < a.nvec;
+  const int64_t v0 = (int64_t)w * K::C;
+  const bool active = v0 + c < a.nvec;
   int64_t base_in, base_out, es_in, es_out;
+  uint32_t lane_in, lane_out;  // point offsets of this lane's vector from the tile bases
   if constexpr (K::COL) {
     // vector v = (grid g, row block k1, column col); element e of the block
     // is row M2*k1 + e on input and row k1 + M1*e on output (M2 = L).
     const int64_t per_g = a.m1 * a.ncols;
-    const int64_t g = v / per_g;
-    const int64_t rem = v - g * per_g;
-    const int64_t k1 = rem / a.ncols;
-    const int64_t col = rem - k1 * a.ncols;
-    const int64_t gbase = g * (int64_t)K::L * per_g;
-    base_in = gbase + k1 * (int64_t)K::L * a.ncols + col;
-    base_out = gbase + k1 * a.ncols + col;
+    auto start = [&](int64_t v, int64_t& in_pt, int64_t& out_pt) {
+      const int64_t g = v / per_g;
+      const int64_t rem = v - g * per_g;
+      const int64_t k1 = rem / a.ncols;
+      const int64_t col = rem - k1 * a.ncols;
+      const int64_t gbase = g * (int64_t)K::L * per_g;
+      in_pt = gbase + k1 * (int64_t)K::L * a.ncols + col;
+      out_pt = gbase + k1 * a.ncols + col;
+    };
+    start(v0, base_in, base_out);
+    if (a.ncols >= K::C) {  // the tile's columns share one grid and row block
+      lane_in = lane_out = (uint32_t)c;
+    } else {
+      int64_t li, lo;
+      start(v0 + c, li, lo);
+      lane_in = (uint32_t)(li - base_in);
+      lane_out = (uint32_t)(lo - base_out);
+    }
     es_in = a.ncols;
     es_out = per_g;
   } else {
-    base_in = base_out = v * K::L;
+    base_in = base_out = v0 * K::L;
+    lane_in = lane_out = (uint32_t)(c * K::L);
     es_in = es_out = 1;
   }
+  const Buf src(a.in + base_in, span_bytes(a.total, base_in));
+  const Buf dst(a.out + base_out, span_bytes(a.total, base_out));
+  const Buf tw(a.tw, (uint32_t)a.tw_count * 8u);
+  const uint32_t voff_in = (lane_in + (uint32_t)(tt * es_in)) * 8u;
+  const uint32_t voff_out = (lane_out + (uint32_t)(tt * es_out)) * 8u;
+  const uint32_t sj_in = (uint32_t)(K::T * es_in) * 8u;
+  const uint32_t sj_out = (uint32_t)(K::T * es_out) * 8u;
   float2 d[K::E];
-  if (active) {
-    static_for<0, K::E>([&](auto J) {
-      constexpr int j = decltype(J)::value;
-      d[j] = gload<NT>(a.in + base_in + (int64_t)(tt + K::T * j) * es_in);
-    });
-    if (io.conj_in) static_for<0, K::E>([&](auto J) { d[decltype(J)::value].y = -d[decltype(J)::value].y; });
-  } else {
-    static_for<0, K::E>([&](auto J) { d[decltype(J)::value] = make_float2(0.f, 0.f); });
-  }
-  static_for<0, K::P>([&](auto Pp) { run_pass<K, DIR, decltype(Pp)::value, SB>(d, lds, tt, c, a.tw); });
+  static_for<0, K::E>([&](auto J) {
+    constexpr int j = decltype(J)::value;
+    d[j] = src.load<NT ? kAuxNontemporal : 0>(voff_in, sj_in * j);
+  });
+  if (io.conj_in) static_for<0, K::E>([&](auto J) { d[decltype(J)::value].y = -d[decltype(J)::value].y; });
+  static_for<0, K::P>([&](auto Pp) { run_pass<K, DIR, decltype(Pp)::value, SB>(d, lds, tt, c, tw); });
   if (active) {
     const float sc = io.scale;
     const float sy = io.conj_out ? -sc : sc;
     static_for<0, K::E>([&](auto J) {
       constexpr int j = decltype(J)::value;
-      gstore<NT>(a.out + base_out + (int64_t)(tt + K::T * j) * es_out, make_float2(d[j].x * sc, d[j].y * sy));
+      dst.store(make_float2(d[j].x * sc, d[j].y * sy), voff_out, sj_out * j);
     });
   }
 }
@@ -386,7 +451,7 @@ __global__ __launch_bounds__(K::THREADS) __attribute__((amdgpu_waves_per_eu(WPE)
 // and the twiddle W_M^(m2 k1), stored to row M2*k1 + m2. The rows' transformed
 // points are exchanged through LDS in Q rounds of L/Q positions; in each round
 // every thread owns L/(Q*THREADS) positions and all M1 rows of each.
-template <class K, int DIR, int WPE = 1, int SB = 0>
+template <class K, int DIR, int WPE = 1, int SB = 0, bool NT = false>
 __global__ __launch_bounds__(K::THREADS) __attribute__((amdgpu_waves_per_eu(WPE))) void rowc_kernel(PassArgs a) {
   static_assert(K::valid() && !K::COL && K::C >= 2 && K::P > 1, "invalid combine configuration");
   constexpr int M1 = K::C;
@@ -401,13 +466,19 @@ __global__ __launch_bounds__(K::THREADS) __attribute__((amdgpu_waves_per_eu(WPE)
   const int64_t g = w / a.m2;
   const int64_t m2 = w - g * a.m2;
   const int64_t gbase = g * a.m2 * M1 * K::L;
-  const float2* src = a.in + gbase + ((int64_t)c * a.m2 + m2) * K::L;
+  // rows M2*c + m2 of grid g: the tile base is row m2, lane rows c*M2 further
+  const int64_t base = gbase + m2 * K::L;
+  const Buf src(a.in + base, span_bytes(a.total, base));
+  const Buf dst(a.out + base, span_bytes(a.total, base));
+  const Buf tw(a.tw, (uint32_t)a.tw_count * 8u);
+  const uint32_t row_bytes = (uint32_t)(a.m2 * K::L) * 8u;  // from row m2 + M2*k to row m2 + M2*(k+1)
+  const uint32_t voff_in = (uint32_t)c * row_bytes + (uint32_t)tt * 8u;
   float2 d[K::E];
   static_for<0, K::E>([&](auto J) {
     constexpr int j = decltype(J)::value;
-    d[j] = src[tt + K::T * j];
+    d[j] = src.load<NT ? kAuxNontemporal : 0>(voff_in, (uint32_t)(K::T * j) * 8u);
   });
-  static_for<0, K::P>([&](auto Pp) { run_pass<K, DIR, decltype(Pp)::value, SB>(d, lds, tt, c, a.tw); });
+  static_for<0, K::P>([&](auto Pp) { run_pass<K, DIR, decltype(Pp)::value, SB>(d, lds, tt, c, tw); });
   float2 wk[M1];
   static_for<1, M1>([&](auto Kk) {
     constexpr int k1 = decltype(Kk)::value;
@@ -418,23 +489,25 @@ __global__ __launch_bounds__(K::THREADS) __attribute__((amdgpu_waves_per_eu(WPE)
   static_for<0, K::Q>([&](auto H) {
     constexpr int h = decltype(H)::value;
     constexpr int EQ = K::E / K::Q;
+    const int wbase = K::lds_index(c, tt);
     static_for<0, EQ>([&](auto J) {
-      constexpr int j = h * EQ + decltype(J)::value;
-      lds[K::lds_index(c, tt + K::T * j - h * NQ)] = d[j];
+      constexpr int jj = decltype(J)::value;
+      lds[wbase + K::lds_delta(K::T * jj)] = d[h * EQ + jj];
     });
     __syncthreads();
+    const int rbase = K::lds_index(0, t);
     static_for<0, NPOS>([&](auto I) {
-      const int p = t + K::THREADS * decltype(I)::value;
+      constexpr int i = decltype(I)::value;
       float2 x[M1];
       static_for<0, M1>([&](auto R) {
         constexpr int r = decltype(R)::value;
-        x[r] = lds[K::lds_index(r, p)];
+        x[r] = lds[rbase + r * K::ROWSTRIDE + K::lds_delta(K::THREADS * i)];
       });
       dft<M1, DIR>(x);
-      float2* dst = a.out + gbase + m2 * K::L + h * NQ + p;
+      const uint32_t voff = (uint32_t)(h * NQ + K::THREADS * i + t) * 8u;
       static_for<0, M1>([&](auto Kk) {
         constexpr int k1 = decltype(Kk)::value;
-        dst[(int64_t)k1 * a.m2 * K::L] = (k1 == 0) ? x[0] : cmul(x[k1], wk[k1]);
+        dst.store((k1 == 0) ? x[0] : cmul(x[k1], wk[k1]), voff, (uint32_t)k1 * row_bytes);
       });
     });
     __syncthreads();
