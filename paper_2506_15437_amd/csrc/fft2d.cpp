@@ -6,7 +6,7 @@
 // row FFTs; here the transposition is the column pass's strided tile access,
 // so the result stays in natural [k][l] order). Each pass is one kernel launch
 // that reads and writes every point once.
-#include "../../include/fft2d.h"
+#include "fft2d.h"
 #include "fft_batched.h"
 #include "fft_internal.h"
 
@@ -442,7 +442,7 @@ fft2d_status fft2d_plan_describe(fft2d_plan_t plan, char* buf, int64_t buflen) {
     for (int i = 0; i < k->npass; ++i) s += (i ? "x" : "") + std::to_string(k->radix[i]);
     s += " E=" + std::to_string(k->E) + " C=" + std::to_string(k->C) + " Q=" + std::to_string(k->Q) +
          " threads=" + std::to_string(k->threads) + " lds=" + std::to_string(k->lds_bytes) +
-         (k->wpe > 1 ? " wpe=" + std::to_string(k->wpe) : "");
+         (k->wpe > 1 ? " wpe=" + std::to_string(k->wpe) : "") + (k->nt ? " nt" : "");
     return s;
   };
   if (plan->kind == kUniform) {

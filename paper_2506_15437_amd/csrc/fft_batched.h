@@ -1,7 +1,7 @@
 // Internal interface of the batched (many shapes, one persistent launch) path.
 #pragma once
 
-#include "../../include/fft2d.h"
+#include "fft2d.h"
 
 #include <hip/hip_runtime.h>
 #include <cstdint>

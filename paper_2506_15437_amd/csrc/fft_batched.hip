@@ -4,18 +4,28 @@
 // Work decomposition. Every transform f (rows M, cols N) becomes row items
 // (tiles of C_row(N) rows; the row FFT of length N) and column items (tiles of
 // C_col(M) columns; the column FFT of length M, in place on the output). A
-// 1 x 1 transform is one copy item. The item list puts every row item before
-// the column items of the same transform, in an order chosen by the
-// autotuner. Persistent workgroups pop items from an atomic queue head; a
-// column item of f waits until f's row-item counter reaches its row-item
-// count. Because every row item of f was popped before any column item of f,
-// and row items never wait, the wait always ends, whatever the number of
-// resident workgroups.
+// 1 x 1 transform is one copy item.
 //
-// Publication of a row item's results: every wave waits for its own stores
-// (s_waitcnt), the workgroup synchronises, then one lane increments f's
-// counter with an agent-scope release. The waiting lane reads the counter
-// with agent-scope acquire before the workgroup loads the data.
+// Queues. Each transform is assigned to one XCD (balanced by its point
+// count), and each XCD has its own queue of item groups (consecutive items of
+// at least a target size). A workgroup reads the XCD it runs on from the
+// XCC_ID hardware register and only pops groups of that XCD's queue, so all
+// items of one transform run on one XCD and share its L2. In every queue the
+// row items of a transform precede its column items.
+//
+// Dependencies. A column item of f waits until f's row-item counter reaches
+// its row-item count. Every row item of f sits earlier in the same queue and
+// was popped by a running workgroup; row items never wait; a workgroup works
+// through its group in order. So the lowest unfinished item can always
+// proceed and every wait ends, whatever the number of resident workgroups.
+// Publication stays inside the XCD: every wave waits until its stores are
+// acknowledged (they are then in the XCD's L2), the workgroup synchronises,
+// one lane increments the counter; the consumer's loads are device-scope
+// loads, which the CU's L1 does not serve. No L2 writeback or invalidation
+// is needed. The plan checks at creation, with a probe launch of the same
+// grid, that the XCC_ID values are 0 .. nq-1 and that every queue has
+// workgroups; if not, it falls back to one queue with agent-scope release /
+// acquire around every counter (correct across XCDs, slower).
 //
 // Direction. The kernel always runs the forward sign; the inverse is
 // conj(F(conj(x))) / (M N): row items conjugate on load, column items
@@ -68,7 +78,7 @@ using BC32 = Cfg<32, 8, 128, 1, true, 8, 4>;
 using BC64 = Cfg<64, 8, 64, 1, true, 8, 8>;
 using BC128 = Cfg<128, 16, 64, 1, true, 16, 8>;
 using BC256 = Cfg<256, 16, 32, 1, true, 16, 16>;
-using BC512 = Cfg<512, 32, 32, 2, true, 16, 32>;
+using BC512 = Cfg<512, 16, 16, 1, true, 16, 16, 2>;
 using BC1024 = Cfg<1024, 32, 16, 2, true, 16, 16, 4>;
 using BC2048 = Cfg<2048, 32, 8, 2, true, 16, 16, 8>;
 using BC4096 = Cfg<4096, 32, 4, 2, true, 16, 16, 16>;
@@ -97,26 +107,36 @@ struct BatchDesc {
 
 enum ItemKind { kRowItem = 0, kColItem = 1, kCopyItem = 2 };
 
+constexpr int kMaxQueues = 8;
+constexpr int kQueueStride = 32;                     // queue heads 128 bytes apart
+constexpr int kCounterBase = kMaxQueues * kQueueStride;  // first per-transform counter
+constexpr int kXccIdReg = (3 << 11) | 20;            // hwreg(HW_REG_XCC_ID, 0, 4)
+
 struct BatchArgs {
   const BatchDesc* desc;
-  const uint2* items;  // x = fft << 2 | kind, y = tile index
-  int n_items;
-  unsigned* counters;  // [0] queue head, [1 + f] finished row items of f, [n_fft + 1] error word
-  const float2* tw;    // concatenated twiddle tables, cfg id -> offset in tw_off
+  const uint2* items;       // x = fft << 2 | kind, y = tile index
+  const uint32_t* groups;   // group g covers items [groups[g], groups[g + 1])
+  int qbeg[kMaxQueues + 1];  // queue x owns groups [qbeg[x], qbeg[x + 1])
+  int nq;                   // number of queues (XCDs)
+  unsigned* counters;       // [x * kQueueStride] head of queue x, [kCounterBase + f] finished row items of f,
+                            // [kCounterBase + n_fft] error word
+  const float2* tw;         // concatenated twiddle tables, cfg id -> offset in tw_off
   int tw_off[kNumCfg];
   int tw_cnt[kNumCfg];
-  int conj;            // 1: inverse transform
-  int n_fft;           // counters[n_fft + 1] is the error word
+  int conj;                 // 1: inverse transform
+  int n_fft;
+  int fenced;               // 1: agent-scope release / acquire (queues not tied to XCDs)
 };
 
 constexpr int kMaxSpins = 1 << 24;
 
 // One configuration's tile as its own (flattened) function, so that every
 // register array of the pass stays in registers inside the large dispatch.
+// Column tiles read the row items' results, so their loads are device-scope.
 template <class K>
 __device__ __noinline__ __attribute__((flatten)) void tile(const PassArgs& pa, int w, float2* lds, TileIO io) {
   static_assert(K::valid() && K::THREADS == kThreads, "batched configurations use 512 threads");
-  fft_tile<K, -1>(pa, w, lds, io);
+  fft_tile<K, -1, K::COL ? kAuxDevice : 0>(pa, w, lds, io);
 }
 
 __device__ __forceinline__ void run_tile(int cfg, const PassArgs& pa, int w, float2* lds, TileIO io) {
@@ -157,83 +177,96 @@ __global__ void clear_counters(unsigned* c, int n) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) c[i] = 0u;
 }
 
+// One word per workgroup: the XCC_ID it ran on (the plan's creation check).
+__global__ void xcc_probe(unsigned* ids) {
+  if (threadIdx.x == 0) ids[blockIdx.x] = (unsigned)__builtin_amdgcn_s_getreg(kXccIdReg);
+}
+
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void batched_kernel(BatchArgs a) {
   __shared__ float2 lds[kLdsElems];
-  __shared__ int s_item;
+  __shared__ int s_group;
+  __shared__ int s_flag;
+  const int xq = (int)((unsigned)__builtin_amdgcn_s_getreg(kXccIdReg) % (unsigned)a.nq);
+  unsigned* head = &a.counters[xq * kQueueStride];
+  const int gend = a.qbeg[xq + 1];
   for (;;) {
-    if (threadIdx.x == 0) s_item = (int)atomicAdd(&a.counters[0], 1u);
+    if (threadIdx.x == 0) s_group = (int)atomicAdd(head, 1u);
     __syncthreads();
-    const int it = __builtin_amdgcn_readfirstlane(s_item);
-    __syncthreads();  // every lane has read s_item before lane 0 may overwrite it
-    if (it >= a.n_items) break;
-    const uint2 item = a.items[it];
-    const int f = (int)(item.x >> 2);
-    const int kind = (int)(item.x & 3u);
-    const BatchDesc d = a.desc[f];
-    const bool inv = a.conj != 0;
-    const float s = inv ? 1.0f / ((float)d.rows * (float)d.cols) : 1.0f;
-    TileIO io;
-    PassArgs pa{};
-    pa.m1 = 1;
-    pa.ncols = d.cols;
-    pa.total = (int64_t)d.rows * d.cols;
-    if (kind == kCopyItem) {
-      if (threadIdx.x == 0) {
-        float2 v = d.in[0];
-        if (inv) v.y = -v.y;
-        d.out[0] = make_float2(v.x * s, inv ? -v.y * s : v.y * s);
-      }
-      continue;
-    }
-    if (kind == kRowItem) {
-      pa.in = d.in;
-      pa.out = d.out;
-      pa.nvec = d.rows;
-      pa.tw = a.tw + a.tw_off[d.row_cfg];
-      pa.tw_count = a.tw_cnt[d.row_cfg];
-      io.conj_in = inv;
-      io.conj_out = inv && d.rows == 1;
-      io.scale = d.rows == 1 ? s : 1.0f;
-      run_tile(d.row_cfg, pa, (int)item.y, lds, io);
-      // publish: own stores complete, workgroup joined, then one release increment
-      __builtin_amdgcn_s_waitcnt(0);
-      __syncthreads();
-      if (threadIdx.x == 0) __hip_atomic_fetch_add(&a.counters[1 + f], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      if (d.nrow_items > 0) {
-        // Bounded wait: the counter always completes (see the file comment); the
-        // bound only guarantees that every wave exits even if that were broken,
-        // in which case the error word is set and the item is skipped.
+    const int g = __builtin_amdgcn_readfirstlane(s_group) + a.qbeg[xq];
+    __syncthreads();  // every lane has read s_group before lane 0 may overwrite it
+    if (g >= gend) break;
+    const int i_end = (int)a.groups[g + 1];
+    for (int it = (int)a.groups[g]; it < i_end; ++it) {
+      const uint2 item = a.items[it];
+      const int f = (int)(item.x >> 2);
+      const int kind = (int)(item.x & 3u);
+      const BatchDesc d = a.desc[f];
+      unsigned* done = &a.counters[kCounterBase + f];
+      const bool inv = a.conj != 0;
+      const float s = inv ? 1.0f / ((float)d.rows * (float)d.cols) : 1.0f;
+      TileIO io;
+      PassArgs pa{};
+      pa.m1 = 1;
+      pa.ncols = d.cols;
+      pa.total = (int64_t)d.rows * d.cols;
+      if (kind == kCopyItem) {
         if (threadIdx.x == 0) {
-          int spins = 0;
-          s_item = 0;
-          while (__hip_atomic_load(&a.counters[1 + f], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) <
-                 (unsigned)d.nrow_items) {
-            __builtin_amdgcn_s_sleep(2);
-            if (++spins > kMaxSpins) {
-              atomicOr(&a.counters[a.n_fft + 1], 1u);
-              s_item = -1;
-              break;
-            }
-          }
+          float2 v = d.in[0];
+          if (inv) v.y = -v.y;
+          d.out[0] = make_float2(v.x * s, inv ? -v.y * s : v.y * s);
         }
-        __syncthreads();
-        const bool timed_out = s_item < 0;
-        __syncthreads();  // every lane has read the flag before lane 0 reuses s_item
-        if (timed_out) continue;
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        continue;
       }
-      pa.in = d.nrow_items > 0 ? d.out : d.in;
-      pa.out = d.out;
-      pa.nvec = d.cols;
-      pa.tw = a.tw + a.tw_off[d.col_cfg];
-      pa.tw_count = a.tw_cnt[d.col_cfg];
-      io.conj_in = inv && d.nrow_items == 0;
-      io.conj_out = inv;
-      io.scale = s;
-      run_tile(d.col_cfg, pa, (int)item.y, lds, io);
+      if (kind == kRowItem) {
+        pa.in = d.in;
+        pa.out = d.out;
+        pa.nvec = d.rows;
+        pa.tw = a.tw + a.tw_off[d.row_cfg];
+        pa.tw_count = a.tw_cnt[d.row_cfg];
+        io.conj_in = inv;
+        io.conj_out = inv && d.rows == 1;
+        io.scale = d.rows == 1 ? s : 1.0f;
+        run_tile(d.row_cfg, pa, (int)item.y, lds, io);
+        // publish: own stores acknowledged by the L2, workgroup joined, one increment
+        if (a.fenced) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (threadIdx.x == 0) __hip_atomic_fetch_add(done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        if (d.nrow_items > 0) {
+          // Bounded wait: the counter always completes (see the file comment);
+          // the bound only guarantees that every wave exits even if that were
+          // broken, in which case the error word is set and the item skipped.
+          if (threadIdx.x == 0) {
+            int spins = 0;
+            s_flag = 0;
+            while (__hip_atomic_load(done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < (unsigned)d.nrow_items) {
+              __builtin_amdgcn_s_sleep(2);
+              if (++spins > kMaxSpins) {
+                atomicOr(&a.counters[kCounterBase + a.n_fft], 1u);
+                s_flag = 1;
+                break;
+              }
+            }
+            if (a.fenced) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+          }
+          __syncthreads();
+          const bool timed_out = s_flag != 0;
+          __syncthreads();
+          if (timed_out) continue;
+        }
+        pa.in = d.nrow_items > 0 ? d.out : d.in;
+        pa.out = d.out;
+        pa.nvec = d.cols;
+        pa.tw = a.tw + a.tw_off[d.col_cfg];
+        pa.tw_count = a.tw_cnt[d.col_cfg];
+        io.conj_in = inv && d.nrow_items == 0;
+        io.conj_out = inv;
+        io.scale = s;
+        run_tile(d.col_cfg, pa, (int)item.y, lds, io);
+      }
+      __syncthreads();  // the LDS of this item is free before the next item starts
     }
-    __syncthreads();  // the LDS of this item is free before the next item starts
   }
 }
 
@@ -270,15 +303,21 @@ struct BatchedPlan {
   int64_t total_points = 0;
   double flops = 0;
   int num_cu = 0;
+  int nq = 1;           // queues = XCDs
+  int fenced = 0;       // 1: queues not tied to XCDs, agent-scope release / acquire
   // tuning choice
   int grid_mult = 2;
   int order = 1;
+  int group_kib = 256;  // target data per item group
   std::string tune_source = "default";
   // device state
   BatchDesc* d_desc = nullptr;
   BatchDesc* h_desc = nullptr;  // pinned staging copy
   uint2* d_items = nullptr;
+  uint32_t* d_groups = nullptr;
   int n_items = 0;
+  int n_groups = 0;
+  int qbeg[kMaxQueues + 1] = {};
   unsigned* d_counters = nullptr;
   float2* d_tw = nullptr;
   int tw_off[kNumCfg] = {};
@@ -292,58 +331,103 @@ struct BatchedPlan {
 
 namespace {
 
-// Item list for a given order policy. 0: every row item, then every column
-// item, transforms largest first. 1: transforms largest first, in chunks of
-// about 64 MiB of data; a chunk's row items, then the previous chunk's column
-// items (so column items mostly read data still in the MALL).
-std::vector<uint2> build_items(const BatchedPlan& bp, int order) {
+struct Schedule {
+  std::vector<uint2> items;
+  std::vector<uint32_t> groups;  // item index where each group starts, plus the end
+  int qbeg[kMaxQueues + 1] = {};
+};
+
+// Points one item moves (its data size / 8 bytes).
+int64_t item_points(const BatchedPlan& bp, const PassKernel* tab, int f, int kind, int t) {
+  const int64_t M = bp.rows[(size_t)f], N = bp.cols[(size_t)f];
+  if (kind == kCopyItem) return 1;
+  if (kind == kRowItem) {
+    const int64_t C = tab[bp.row_cfg[(size_t)f]].C;
+    return std::min<int64_t>(C, M - (int64_t)t * C) * N;
+  }
+  const int64_t C = tab[bp.col_cfg[(size_t)f]].C;
+  return std::min<int64_t>(C, N - (int64_t)t * C) * M;
+}
+
+// Build the queues. Transforms go to the XCD with the least assigned points
+// (largest first). Within a queue, order 0 lists every row item and then every
+// column item (largest transforms first); order 1 works in chunks of about
+// 16 MiB per queue: a chunk's row items, then the previous chunk's column
+// items (which then mostly read data still in the MALL). Consecutive items
+// form groups of at least group_kib KiB of data; a workgroup pops one group.
+Schedule build_schedule(const BatchedPlan& bp, int order, int group_kib) {
+  const PassKernel* tab = cfg_table();
   std::vector<int> idx((size_t)bp.count);
   for (int64_t i = 0; i < bp.count; ++i) idx[(size_t)i] = (int)i;
-  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
-    return (int64_t)bp.rows[a] * bp.cols[a] > (int64_t)bp.rows[b] * bp.cols[b];
-  });
+  auto pts = [&](int f) { return (int64_t)bp.rows[(size_t)f] * bp.cols[(size_t)f]; };
+  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return pts(a) > pts(b); });
+  std::vector<std::vector<int>> q((size_t)bp.nq);
+  std::vector<int64_t> load((size_t)bp.nq, 0);
+  for (int f : idx) {
+    const size_t x = (size_t)(std::min_element(load.begin(), load.end()) - load.begin());
+    q[x].push_back(f);
+    load[x] += pts(f);
+  }
+  Schedule sc;
   auto rows_of = [&](int f, std::vector<uint2>& out) {
-    if (bp.rows[f] == 1 && bp.cols[f] == 1) {
+    if (bp.rows[(size_t)f] == 1 && bp.cols[(size_t)f] == 1) {
       out.push_back(make_uint2((unsigned)f << 2 | kCopyItem, 0));
       return;
     }
-    for (int t = 0; t < bp.nrow[f]; ++t) out.push_back(make_uint2((unsigned)f << 2 | kRowItem, (unsigned)t));
+    for (int t = 0; t < bp.nrow[(size_t)f]; ++t) out.push_back(make_uint2((unsigned)f << 2 | kRowItem, (unsigned)t));
   };
   auto cols_of = [&](int f, std::vector<uint2>& out) {
-    for (int t = 0; t < bp.ncol[f]; ++t) out.push_back(make_uint2((unsigned)f << 2 | kColItem, (unsigned)t));
+    for (int t = 0; t < bp.ncol[(size_t)f]; ++t) out.push_back(make_uint2((unsigned)f << 2 | kColItem, (unsigned)t));
   };
-  std::vector<uint2> items;
-  if (order == 0) {
-    for (int f : idx) rows_of(f, items);
-    for (int f : idx) cols_of(f, items);
-    return items;
-  }
-  const int64_t chunk_points = (int64_t(64) << 20) / 8;
-  std::vector<int> prev, cur;
-  int64_t acc = 0;
-  for (size_t k = 0; k < idx.size(); ++k) {
-    const int f = idx[k];
-    rows_of(f, items);
-    cur.push_back(f);
-    acc += (int64_t)bp.rows[f] * bp.cols[f];
-    if (acc >= chunk_points || k + 1 == idx.size()) {
+  const int64_t target = (int64_t)group_kib * 1024 / 8;
+  for (int x = 0; x < bp.nq; ++x) {
+    std::vector<uint2> items;
+    if (order == 0) {
+      for (int f : q[(size_t)x]) rows_of(f, items);
+      for (int f : q[(size_t)x]) cols_of(f, items);
+    } else {
+      const int64_t chunk_points = (int64_t(16) << 20) / 8;
+      std::vector<int> prev, cur;
+      int64_t acc = 0;
+      for (size_t k = 0; k < q[(size_t)x].size(); ++k) {
+        const int f = q[(size_t)x][k];
+        rows_of(f, items);
+        cur.push_back(f);
+        acc += pts(f);
+        if (acc >= chunk_points || k + 1 == q[(size_t)x].size()) {
+          for (int g : prev) cols_of(g, items);
+          prev.swap(cur);
+          cur.clear();
+          acc = 0;
+        }
+      }
       for (int g : prev) cols_of(g, items);
-      prev.swap(cur);
-      cur.clear();
-      acc = 0;
+    }
+    sc.qbeg[x] = (int)sc.groups.size();
+    int64_t acc = target;  // open a new group at the first item
+    for (const uint2& it : items) {
+      if (acc >= target) {
+        sc.groups.push_back((uint32_t)sc.items.size());
+        acc = 0;
+      }
+      acc += item_points(bp, tab, (int)(it.x >> 2), (int)(it.x & 3u), (int)it.y);
+      sc.items.push_back(it);
     }
   }
-  for (int g : prev) cols_of(g, items);
-  return items;
+  for (int x = bp.nq; x <= kMaxQueues; ++x) sc.qbeg[x] = (int)sc.groups.size();
+  sc.groups.push_back((uint32_t)sc.items.size());
+  return sc;
 }
 
 hipError_t launch_batched(BatchedPlan* bp, int conj, int grid, hipStream_t s) {
-  const int nc = (int)bp->count + 2;
+  const int nc = kCounterBase + (int)bp->count + 1;
   hipLaunchKernelGGL(clear_counters, dim3((unsigned)std::min(64, (nc + 255) / 256)), dim3(256), 0, s, bp->d_counters, nc);
   BatchArgs a{};
   a.desc = bp->d_desc;
   a.items = bp->d_items;
-  a.n_items = bp->n_items;
+  a.groups = bp->d_groups;
+  for (int x = 0; x <= kMaxQueues; ++x) a.qbeg[x] = bp->qbeg[x];
+  a.nq = bp->nq;
   a.counters = bp->d_counters;
   a.tw = bp->d_tw;
   const PassKernel* tab = cfg_table();
@@ -353,17 +437,26 @@ hipError_t launch_batched(BatchedPlan* bp, int conj, int grid, hipStream_t s) {
   }
   a.conj = conj;
   a.n_fft = (int)bp->count;
+  a.fenced = bp->fenced;
   hipLaunchKernelGGL(batched_kernel, dim3((unsigned)grid), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
 
-hipError_t upload_items(BatchedPlan* bp, const std::vector<uint2>& items) {
+hipError_t upload_schedule(BatchedPlan* bp, const Schedule& sc) {
   if (bp->d_items) (void)hipFree(bp->d_items);
+  if (bp->d_groups) (void)hipFree(bp->d_groups);
   bp->d_items = nullptr;
-  bp->n_items = (int)items.size();
-  hipError_t e = hipMalloc((void**)&bp->d_items, std::max<size_t>(1, items.size()) * sizeof(uint2));
+  bp->d_groups = nullptr;
+  bp->n_items = (int)sc.items.size();
+  bp->n_groups = (int)sc.groups.size() - 1;
+  for (int x = 0; x <= kMaxQueues; ++x) bp->qbeg[x] = sc.qbeg[x];
+  hipError_t e = hipMalloc((void**)&bp->d_items, std::max<size_t>(1, sc.items.size()) * sizeof(uint2));
   if (e != hipSuccess) return e;
-  return hipMemcpy(bp->d_items, items.data(), items.size() * sizeof(uint2), hipMemcpyHostToDevice);
+  e = hipMemcpy(bp->d_items, sc.items.data(), sc.items.size() * sizeof(uint2), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return e;
+  e = hipMalloc((void**)&bp->d_groups, sc.groups.size() * sizeof(uint32_t));
+  if (e != hipSuccess) return e;
+  return hipMemcpy(bp->d_groups, sc.groups.data(), sc.groups.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
 }
 
 std::string shape_signature(const BatchedPlan& bp) {
@@ -391,8 +484,10 @@ std::string cache_path() {
   return std::string(home) + "/.cache/fft2d_tune.txt";
 }
 
-// Cache lines: "<key hex> <grid_mult> <order>"; malformed lines are ignored.
-bool cache_lookup(const std::string& key, int* mult, int* order) {
+bool valid_group_kib(int g) { return g == 64 || g == 256 || g == 1024; }
+
+// Cache lines: "<key hex> <grid_mult> <order> <group_kib>"; malformed lines are ignored.
+bool cache_lookup(const std::string& key, int* mult, int* order, int* group_kib) {
   const std::string path = cache_path();
   if (path.empty()) return false;
   std::ifstream in(path);
@@ -401,18 +496,19 @@ bool cache_lookup(const std::string& key, int* mult, int* order) {
   while (std::getline(in, line)) {
     std::istringstream ls(line);
     std::string k;
-    int m = 0, o = -1;
-    if (!(ls >> k >> m >> o)) continue;
-    if (k == key && m >= 1 && m <= 8 && (o == 0 || o == 1)) {
+    int m = 0, o = -1, g = 0;
+    if (!(ls >> k >> m >> o >> g)) continue;
+    if (k == key && m >= 1 && m <= 4 && (o == 0 || o == 1) && valid_group_kib(g)) {
       *mult = m;
       *order = o;
+      *group_kib = g;
       found = true;
     }
   }
   return found;
 }
 
-void cache_store(const std::string& key, int mult, int order) {
+void cache_store(const std::string& key, int mult, int order, int group_kib) {
   const std::string path = cache_path();
   if (path.empty()) return;
   std::ofstream out(path, std::ios::app);
@@ -422,12 +518,13 @@ void cache_store(const std::string& key, int mult, int order) {
     (void)::mkdir(path.substr(0, slash).c_str(), 0755);  // one level, best effort
     out.open(path, std::ios::app);
   }
-  if (out) out << key << " " << mult << " " << order << "\n";
+  if (out) out << key << " " << mult << " " << order << " " << group_kib << "\n";
 }
 
-// Time one candidate (grid multiplier, order) on scratch buffers; median of reps.
-float time_candidate(BatchedPlan* bp, int mult, int order, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-  if (upload_items(bp, build_items(*bp, order)) != hipSuccess) return 1e30f;
+// Time one candidate (grid multiplier, order, group size) on scratch buffers; median of reps.
+float time_candidate(BatchedPlan* bp, int mult, int order, int group_kib, hipStream_t s, hipEvent_t e0,
+                     hipEvent_t e1) {
+  if (upload_schedule(bp, build_schedule(*bp, order, group_kib)) != hipSuccess) return 1e30f;
   std::vector<float> ts;
   for (int r = 0; r < 4; ++r) {
     (void)hipEventRecord(e0, s);
@@ -482,6 +579,47 @@ fft2d_status create_batched(int64_t count, const int64_t* rows, const int64_t* c
   if (e != hipSuccess) return hipfail(e, "hipGetDevice");
   e = hipDeviceGetAttribute(&bp->num_cu, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return hipfail(e, "hipDeviceGetAttribute");
+  if ((e = hipStreamCreateWithFlags(&bp->cap_stream, hipStreamNonBlocking)) != hipSuccess) return hipfail(e, "stream");
+  if ((e = hipEventCreateWithFlags(&bp->staged, hipEventDisableTiming)) != hipSuccess) return hipfail(e, "event");
+  // Queue layout. One queue per XCD when probe launches of every candidate
+  // grid see XCC_ID values 0 .. k-1, each of them; otherwise one queue with
+  // agent-scope release / acquire. FFT2D_BATCH_SYNC=fenced forces the latter.
+  {
+    const int gmax = 3 * bp->num_cu;
+    unsigned* ids = nullptr;
+    if ((e = hipMalloc((void**)&ids, (size_t)gmax * sizeof(unsigned))) != hipSuccess) return hipfail(e, "probe");
+    std::vector<unsigned> h((size_t)gmax);
+    int k = 0;
+    bool ok = true;
+    for (int m = 1; m <= 3 && ok && e == hipSuccess; ++m) {
+      const int g = m * bp->num_cu;
+      hipLaunchKernelGGL(xcc_probe, dim3((unsigned)g), dim3(64), 0, bp->cap_stream, ids);
+      if ((e = hipGetLastError()) != hipSuccess) break;
+      if ((e = hipStreamSynchronize(bp->cap_stream)) != hipSuccess) break;
+      if ((e = hipMemcpy(h.data(), ids, (size_t)g * sizeof(unsigned), hipMemcpyDeviceToHost)) != hipSuccess) break;
+      unsigned mx = 0;
+      for (int i = 0; i < g; ++i) mx = std::max(mx, h[(size_t)i]);
+      if (mx >= (unsigned)kMaxQueues) {
+        ok = false;
+        break;
+      }
+      std::vector<int> seen(mx + 1, 0);
+      for (int i = 0; i < g; ++i) ++seen[h[(size_t)i]];
+      if (m == 1) k = (int)mx + 1;
+      ok = (int)mx + 1 == k && std::find(seen.begin(), seen.end(), 0) == seen.end();
+    }
+    (void)hipFree(ids);
+    if (e != hipSuccess) return hipfail(e, "XCC probe");
+    const char* sync_env = std::getenv("FFT2D_BATCH_SYNC");
+    const bool force_fenced = sync_env && std::string(sync_env) == "fenced";
+    if (ok && !force_fenced) {
+      bp->nq = k;
+      bp->fenced = 0;
+    } else {
+      bp->nq = 1;
+      bp->fenced = 1;
+    }
+  }
   // twiddle tables of every configuration (all, so a pointer change never needs new tables)
   {
     std::vector<float2> host;
@@ -501,10 +639,8 @@ fft2d_status create_batched(int64_t count, const int64_t* rows, const int64_t* c
     return hipfail(e, "descriptor table");
   if ((e = hipHostMalloc((void**)&bp->h_desc, (size_t)count * sizeof(BatchDesc), hipHostMallocDefault)) != hipSuccess)
     return hipfail(e, "pinned descriptor staging");
-  if ((e = hipMalloc((void**)&bp->d_counters, (size_t)(count + 2) * sizeof(unsigned))) != hipSuccess)
+  if ((e = hipMalloc((void**)&bp->d_counters, (size_t)(kCounterBase + count + 1) * sizeof(unsigned))) != hipSuccess)
     return hipfail(e, "counters");
-  if ((e = hipStreamCreateWithFlags(&bp->cap_stream, hipStreamNonBlocking)) != hipSuccess) return hipfail(e, "stream");
-  if ((e = hipEventCreateWithFlags(&bp->staged, hipEventDisableTiming)) != hipSuccess) return hipfail(e, "event");
   for (int64_t i = 0; i < count; ++i) {
     BatchDesc& d = bp->h_desc[i];
     d.in = nullptr;
@@ -522,14 +658,14 @@ fft2d_status create_batched(int64_t count, const int64_t* rows, const int64_t* c
   const char* tune_env = std::getenv("FFT2D_TUNE");
   const std::string mode = tune_env ? tune_env : "cached";
   std::ostringstream keys;
-  keys << "gfx950|v1|" << shape_signature(*bp);
+  keys << "gfx950|v2|" << shape_signature(*bp);
   char keyhex[32];
   std::snprintf(keyhex, sizeof(keyhex), "%016llx", (unsigned long long)fnv1a(keys.str()));
   bool have = false;
   if (mode == "off") {
     have = true;
     bp->tune_source = "default";
-  } else if (mode != "full" && cache_lookup(keyhex, &bp->grid_mult, &bp->order)) {
+  } else if (mode != "full" && cache_lookup(keyhex, &bp->grid_mult, &bp->order, &bp->group_kib)) {
     have = true;
     bp->tune_source = "cache";
   }
@@ -556,15 +692,18 @@ fft2d_status create_batched(int64_t count, const int64_t* rows, const int64_t* c
     float best = 1e30f;
     if (e == hipSuccess) {
       const int mults[] = {1, 2, 3};
+      const int gks[] = {64, 256, 1024};
       for (int m : mults)
-        for (int o = 0; o < 2; ++o) {
-          const float t = time_candidate(bp, m, o, bp->cap_stream, e0, e1);
-          if (t < best) {
-            best = t;
-            bp->grid_mult = m;
-            bp->order = o;
+        for (int o = 0; o < 2; ++o)
+          for (int g : gks) {
+            const float t = time_candidate(bp, m, o, g, bp->cap_stream, e0, e1);
+            if (t < best) {
+              best = t;
+              bp->grid_mult = m;
+              bp->order = o;
+              bp->group_kib = g;
+            }
           }
-        }
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
@@ -575,9 +714,10 @@ fft2d_status create_batched(int64_t count, const int64_t* rows, const int64_t* c
     if (e != hipSuccess) return hipfail(e, "autotune");
     if (best >= 1e29f) return fail(FFT2D_ERR_HIP, "autotune: every candidate failed");
     bp->tune_source = "tuned";
-    cache_store(keyhex, bp->grid_mult, bp->order);
+    cache_store(keyhex, bp->grid_mult, bp->order, bp->group_kib);
   }
-  if ((e = upload_items(bp, build_items(*bp, bp->order))) != hipSuccess) return hipfail(e, "item table");
+  if ((e = upload_schedule(bp, build_schedule(*bp, bp->order, bp->group_kib))) != hipSuccess)
+    return hipfail(e, "item table");
 
   // One graph per direction: counter clear (a kernel, no memset node) + the persistent kernel.
   for (int dir = 0; dir < 2; ++dir) {
@@ -657,6 +797,7 @@ void destroy_batched(BatchedPlan* bp) {
   if (bp->d_desc) (void)hipFree(bp->d_desc);
   if (bp->h_desc) (void)hipHostFree(bp->h_desc);
   if (bp->d_items) (void)hipFree(bp->d_items);
+  if (bp->d_groups) (void)hipFree(bp->d_groups);
   if (bp->d_counters) (void)hipFree(bp->d_counters);
   if (bp->d_tw) (void)hipFree(bp->d_tw);
   delete bp;
@@ -665,8 +806,10 @@ void destroy_batched(BatchedPlan* bp) {
 std::string describe_batched(const BatchedPlan* bp) {
   std::ostringstream os;
   os << "batched count=" << bp->count << " points=" << bp->total_points << " items=" << bp->n_items
-     << " grid=" << bp->grid_mult << "x" << bp->num_cu << " order=" << (bp->order ? "chunked" : "rows-then-columns")
-     << " tune=" << bp->tune_source << " threads=" << kThreads << " lds=" << kLdsElems * 8;
+     << " groups=" << bp->n_groups << " group_kib=" << bp->group_kib << " queues=" << bp->nq
+     << (bp->fenced ? " fenced" : " xcd-local") << " grid=" << bp->grid_mult << "x" << bp->num_cu
+     << " order=" << (bp->order ? "chunked" : "rows-then-columns") << " tune=" << bp->tune_source
+     << " threads=" << kThreads << " lds=" << kLdsElems * 8;
   return os.str();
 }
 

@@ -45,6 +45,7 @@ struct PassKernel {
   int colmode;
   int combine;  // row pass with an M1 = C point combine across its rows (split column transform)
   int wpe;  // minimum waves per SIMD the kernel was compiled for
+  int nt;   // nontemporal input loads
   int npass;
   int radix[kMaxPasses];
   size_t lds_bytes;

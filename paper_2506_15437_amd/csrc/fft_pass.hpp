@@ -139,6 +139,7 @@ __device__ __forceinline__ void gstore(float2* p, float2 v) {
 // `bytes` read zero and drop stores (hardware range check).
 constexpr int kBufferDword3 = 0x00020000;
 constexpr int kAuxNontemporal = 2;
+constexpr int kAuxDevice = 16;  // sc1: device-scope load, not served from the CU's L1
 
 struct Buf {
   __amdgpu_buffer_rsrc_t r;
@@ -373,7 +374,8 @@ struct TileIO {
 // wave-uniform). Global memory is reached through buffer resources based at
 // the tile's first point, so every lane needs one 32-bit offset register and
 // the E points differ by uniform offsets.
-template <class K, int DIR, bool NT = false, int SB = 0>
+// AUX: cache policy of the input loads (0, kAuxNontemporal, or kAuxDevice).
+template <class K, int DIR, int AUX = 0, int SB = 0>
 __device__ __forceinline__ void fft_tile(const PassArgs& a, int w, float2* lds, TileIO io) {
   const int t = threadIdx.x;
   const int c = K::COL ? (t % K::C) : (t / K::T);
@@ -421,7 +423,7 @@ __device__ __forceinline__ void fft_tile(const PassArgs& a, int w, float2* lds, 
   float2 d[K::E];
   static_for<0, K::E>([&](auto J) {
     constexpr int j = decltype(J)::value;
-    d[j] = src.load<NT ? kAuxNontemporal : 0>(voff_in, sj_in * j);
+    d[j] = src.load<AUX>(voff_in, sj_in * j);
   });
   if (io.conj_in) static_for<0, K::E>([&](auto J) { d[decltype(J)::value].y = -d[decltype(J)::value].y; });
   static_for<0, K::P>([&](auto Pp) { run_pass<K, DIR, decltype(Pp)::value, SB>(d, lds, tt, c, tw); });
@@ -442,7 +444,7 @@ __global__ __launch_bounds__(K::THREADS) __attribute__((amdgpu_waves_per_eu(WPE)
   const int w = K::COL ? xcd_remap(blockIdx.x, a.nblocks) : (int)blockIdx.x;
   TileIO io;
   io.scale = a.scale;
-  fft_tile<K, DIR, NT, SB>(a, w, lds, io);
+  fft_tile<K, DIR, NT ? kAuxNontemporal : 0, SB>(a, w, lds, io);
 }
 
 // Row pass with combine (first half of a split column transform, see
@@ -514,17 +516,17 @@ __global__ __launch_bounds__(K::THREADS) __attribute__((amdgpu_waves_per_eu(WPE)
   });
 }
 
-template <class K, int WPE>
+template <class K, int WPE, bool NT>
 hipError_t launch_pass(const PassArgs& a, int dir, hipStream_t s) {
-  if (dir < 0) hipLaunchKernelGGL((pass_kernel<K, -1, false, WPE>), dim3(a.nblocks), dim3(K::THREADS), 0, s, a);
-  else hipLaunchKernelGGL((pass_kernel<K, +1, false, WPE>), dim3(a.nblocks), dim3(K::THREADS), 0, s, a);
+  if (dir < 0) hipLaunchKernelGGL((pass_kernel<K, -1, NT, WPE>), dim3(a.nblocks), dim3(K::THREADS), 0, s, a);
+  else hipLaunchKernelGGL((pass_kernel<K, +1, NT, WPE>), dim3(a.nblocks), dim3(K::THREADS), 0, s, a);
   return hipGetLastError();
 }
 
-template <class K, int WPE>
+template <class K, int WPE, bool NT>
 hipError_t launch_rowc(const PassArgs& a, int dir, hipStream_t s) {
-  if (dir < 0) hipLaunchKernelGGL((rowc_kernel<K, -1, WPE>), dim3(a.nblocks), dim3(K::THREADS), 0, s, a);
-  else hipLaunchKernelGGL((rowc_kernel<K, +1, WPE>), dim3(a.nblocks), dim3(K::THREADS), 0, s, a);
+  if (dir < 0) hipLaunchKernelGGL((rowc_kernel<K, -1, WPE, 0, NT>), dim3(a.nblocks), dim3(K::THREADS), 0, s, a);
+  else hipLaunchKernelGGL((rowc_kernel<K, +1, WPE, 0, NT>), dim3(a.nblocks), dim3(K::THREADS), 0, s, a);
   return hipGetLastError();
 }
 
@@ -547,7 +549,9 @@ constexpr PassKernel meta() {
 }
 
 // WPE: minimum waves per SIMD the compiler must allow (bounds VGPR use).
-template <class K, bool COMBINE = false, int WPE = 1>
+// NT: nontemporal loads of the input (row passes read data not reused soon;
+// measured faster from HBM, slower when the data already sits in the MALL).
+template <class K, bool COMBINE = false, int WPE = 1, bool NT = !K::COL>
 constexpr PassKernel describe() {
   PassKernel k{};
   k.combine = COMBINE ? K::C : 0;
@@ -562,8 +566,9 @@ constexpr PassKernel describe() {
   for (int p = 0; p < kMaxPasses; ++p) k.radix[p] = p < K::P ? K::radix(p) : 0;
   k.lds_bytes = (size_t)K::LDS_ELEMS * 8;
   k.wpe = WPE;
-  if constexpr (COMBINE) k.launch = &launch_rowc<K, WPE>;
-  else k.launch = &launch_pass<K, WPE>;
+  k.nt = NT ? 1 : 0;
+  if constexpr (COMBINE) k.launch = &launch_rowc<K, WPE, NT>;
+  else k.launch = &launch_pass<K, WPE, NT>;
   return k;
 }
 

@@ -38,14 +38,18 @@ def _run(F, plan, xs, direction, outs=None):
     return ins, res
 
 
-@pytest.mark.parametrize("tune", ["off", "full"])
-def test_batched_mixed_shapes(F, tune, monkeypatch):
+@pytest.mark.parametrize("tune,sync", [("off", "auto"), ("full", "auto"), ("off", "fenced")])
+def test_batched_mixed_shapes(F, tune, sync, monkeypatch):
+    """Forward and inverse of every length 1 .. 16384 as rows and as columns;
+    sync "fenced" forces the single-queue path with agent-scope release / acquire."""
     monkeypatch.setenv("FFT2D_TUNE", tune)
-    say("case batched mixed shapes tune=%s" % tune)
+    monkeypatch.setenv("FFT2D_BATCH_SYNC", sync)
+    say("case batched mixed shapes tune=%s sync=%s" % (tune, sync))
     xs = synth.batched_grids(11, MIXED)
     plan = F.BatchedPlan(MIXED)
     try:
         say(plan.describe())
+        assert ("fenced" in plan.describe()) == (sync == "fenced")
         _, ys = _run(F, plan, xs, F.FORWARD)
         _, zs = _run(F, plan, xs, F.INVERSE)
         worst_f = worst_i = 0.0
