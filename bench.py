@@ -33,8 +33,101 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_POINT_PER_PASS = 16  # each pass reads and writes every complex64 point once
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hbm_traffic_fft2d_4096x4096_roundtrip.txt")
+PASS_NAMES = ["fwd_row", "fwd_col", "inv_row", "inv_col"]
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    """SHA-256 over the sources of the plain path (kernels, plan logic, public
+    header): counters taken from an older build do not describe the current one."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2506_15437_amd", "csrc")
+    files = sorted(f for f in os.listdir(csrc)
+                   if f.endswith((".hip", ".hpp", ".h", ".cpp")) and not f.startswith("fft_batched"))
+    for f in files + ["fft2d.h"]:
+        path = os.path.join(csrc, f) if f != "fft2d.h" else os.path.join(ROOT, "include", "fft2d.h")
+        with open(path, "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
+
+
+def _counter_rows(run_dir):
+    import csv
+    path = os.path.join(run_dir, "run_counter_collection.csv")
+    with open(path, newline="") as fh:
+        return list(csv.DictReader(fh))
+
+
+def summarize_traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir):
+    """HBM bytes per launch of each pass from rocprofv3 FETCH_SIZE / WRITE_SIZE
+    runs (KiB per dispatch), each scaled by the factor that makes the same
+    counter read the known size of a plain device copy (bench.py --copy-only)."""
+    copy_bytes = 4096 * 4096 * 8  # bytes read, and bytes written, by one copy of the grid
+    factors = {}
+    for name, d in (("FETCH_SIZE", copy_fetch_dir), ("WRITE_SIZE", copy_write_dir)):
+        vals = [float(r["Counter_Value"]) for r in _counter_rows(d)
+                if "copyBuffer" in r["Kernel_Name"] and r["Counter_Name"] == name]
+        kib = float(np.median(vals))
+        factors[name] = (copy_bytes / 1024.0) / kib
+    per_pass = {}
+    for name, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        rows = [r for r in _counter_rows(d) if "fft2d::dev::" in r["Kernel_Name"] and r["Counter_Name"] == name]
+        rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+        for i, r in enumerate(rows):
+            p = PASS_NAMES[i % 4]
+            per_pass.setdefault(p, {}).setdefault(name, []).append(float(r["Counter_Value"]))
+            per_pass[p]["kernel"] = r["Kernel_Name"]
+    lines = ["source_hash = %s" % kernel_source_hash(),
+             "fetch_factor = %.4f" % factors["FETCH_SIZE"],
+             "write_factor = %.4f" % factors["WRITE_SIZE"],
+             "algorithmic_bytes_per_pass = %d" % (BYTES_PER_POINT_PER_PASS * 4096 * 4096)]
+    for p in PASS_NAMES:
+        e = per_pass[p]
+        fk = float(np.mean(e["FETCH_SIZE"]))
+        wk = float(np.mean(e["WRITE_SIZE"]))
+        rd = fk * 1024 * factors["FETCH_SIZE"]
+        wr = wk * 1024 * factors["WRITE_SIZE"]
+        lines.append("pass %s bytes %d read %d write %d fetch_kib %.1f write_kib %.1f dispatches %d kernel %s"
+                     % (p, rd + wr, rd, wr, fk, wk, len(e["FETCH_SIZE"]), e["kernel"]))
+    return "\n".join(lines)
+
+
+def summarize_stats(stats_dir):
+    """The fft2d rows of a rocprofv3 --kernel-trace --stats run (kernel_stats.csv)."""
+    import csv
+    with open(os.path.join(stats_dir, "run_kernel_stats.csv"), newline="") as fh:
+        rows = list(csv.DictReader(fh))
+    out = ["calls  avg_us   min_us   max_us   total_%  kernel"]
+    for r in rows:
+        out.append("%5s %8.2f %8.2f %8.2f %8.2f  %s" % (r["Calls"], float(r["AverageNs"]) / 1e3,
+                                                      float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3,
+                                                      float(r["Percentage"]), r["Name"]))
+    return "\n".join(out)
+
+
+def measured_traffic(pass_name):
+    """HBM bytes per launch of `pass_name` from the committed counter summary,
+    or None when it is missing or was taken from other kernel sources."""
+    try:
+        with open(TRAFFIC_PROFILE) as fh:
+            text = fh.read()
+    except OSError:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        f = line.split()
+        if len(f) >= 3 and f[1] == "=":
+            vals[f[0]] = f[2]
+        elif len(f) >= 4 and f[0] == "pass" and f[2] == "bytes":
+            vals["pass " + f[1]] = f[3]
+    if vals.get("source_hash") != kernel_source_hash() or ("pass " + pass_name) not in vals:
+        return None
+    return int(vals["pass " + pass_name])
 
 
 def flops_2d(rows, cols, batch=1):
@@ -193,7 +286,17 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the backward and batched comparisons")
     ap.add_argument("--copy-only", action="store_true",
                     help="only run plain device copies of the 4096x4096 grid (calibrates rocprofv3 byte counters)")
+    ap.add_argument("--summarize-traffic", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
+                    help="print HBM bytes per pass from four rocprofv3 --pmc output folders, then exit")
+    ap.add_argument("--summarize-stats", metavar="DIR",
+                    help="print the kernel rows of a rocprofv3 --kernel-trace --stats output folder, then exit")
     args = ap.parse_args()
+    if args.summarize_traffic:
+        print(summarize_traffic(*args.summarize_traffic))
+        return
+    if args.summarize_stats:
+        print(summarize_stats(args.summarize_stats))
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -222,7 +325,7 @@ def main():
     ms_per_step = r["wall"] / args.steps * 1e3
     step_flops = 2 * flops_2d(rows, cols)
     value = step_flops / (ms_per_step * 1e-3) / 1e9
-    pass_names = ["fwd_row", "fwd_col", "inv_row", "inv_col"]
+    pass_names = PASS_NAMES
     mean_pass = r["per_pass_ms"].mean(axis=0)
     pass_bytes = BYTES_PER_POINT_PER_PASS * rows * cols
     dom = int(np.argmax(mean_pass))
@@ -249,7 +352,7 @@ def main():
         "hbm_gbps_effective": round(step_bytes / (ms_per_step * 1e-3) / 1e9, 1),
         "roofline": {"bound": "hbm", "kernel": pass_names[dom] + " pass", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None},
+                     "traffic": measured_traffic(pass_names[dom])},
         "per_pass_ms": {n: round(float(v), 5) for n, v in zip(pass_names, mean_pass)},
         "per_pass_gbps": {n: round(pass_bytes / (float(v) * 1e-3) / 1e9, 1) for n, v in zip(pass_names, mean_pass)},
         "roundtrip_rel_l2": r["roundtrip_rel_l2"],
@@ -264,7 +367,7 @@ def main():
 
     if not args.no_cpu:
         log("bench: CPU baseline (FP64 oracle)")
-        ref, cpu = cpu_baseline(rows, cols, r["x"], args.cpu_budget, 20)
+        ref, cpu = cpu_baseline(rows, cols, r["x"], args.cpu_budget, 200)
         result["cpu_baseline"] = cpu
         num = np.linalg.norm((r["y"].astype(np.complex128) - ref).ravel())
         result["fwd_rel_l2_vs_oracle"] = float(num / np.linalg.norm(ref.ravel()))
