@@ -59,7 +59,8 @@ typedef enum fft2d_status {
   FFT2D_ERR_OUT_OF_MEMORY = 6,     /* plan creation could not allocate host or device memory */
   FFT2D_ERR_HIP = 7,               /* a HIP runtime call failed; see fft2d_last_error() */
   FFT2D_ERR_INVALID_PLAN = 8,      /* the handle is not a live plan (e.g. already destroyed) */
-  FFT2D_ERR_OVERLAP = 9            /* input and output partially overlap (exact aliasing is allowed) */
+  FFT2D_ERR_OVERLAP = 9,           /* input and output partially overlap (exact aliasing is allowed) */
+  FFT2D_ERR_INCOMPLETE = 10        /* an earlier fft2d_exec_batched on this plan gave up a bounded wait */
 } fft2d_status;
 
 /* Opaque plan handle, owned by the library until fft2d_destroy(). */
@@ -113,6 +114,12 @@ fft2d_status fft2d_exec(fft2d_plan_t plan, const void* in, void* out, int direct
  *             previous call's, the device descriptor table is refreshed by a
  *             stream-ordered copy before the launch.
  *   direction, stream : as for fft2d_exec.
+ * The persistent kernel's waits (a column tile waits for its grid's row
+ * tiles) always end by construction; each is still bounded (about a second
+ * of polling) so the launch drains even if that were broken. A wait that gives
+ * up skips its tile and sets a flag in pinned host memory; the next call on
+ * the plan then returns FFT2D_ERR_INCOMPLETE without launching (and clears the
+ * flag), since the outputs of the earlier call are incomplete.
  */
 fft2d_status fft2d_exec_batched(fft2d_plan_t plan, const void* const* in, void* const* out, int direction,
                                 void* stream);

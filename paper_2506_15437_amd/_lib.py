@@ -33,6 +33,7 @@ STATUS_NAMES = {
     7: "FFT2D_ERR_HIP",
     8: "FFT2D_ERR_INVALID_PLAN",
     9: "FFT2D_ERR_OVERLAP",
+    10: "FFT2D_ERR_INCOMPLETE",
 }
 
 # Every symbol the public header declares.

@@ -425,6 +425,7 @@ const char* fft2d_status_string(fft2d_status st) {
     case FFT2D_ERR_HIP: return "HIP runtime error";
     case FFT2D_ERR_INVALID_PLAN: return "invalid plan";
     case FFT2D_ERR_OVERLAP: return "overlapping buffers";
+    case FFT2D_ERR_INCOMPLETE: return "incomplete earlier execution";
   }
   return "unknown status";
 }

@@ -118,17 +118,18 @@ struct BatchArgs {
   const uint32_t* groups;   // group g covers items [groups[g], groups[g + 1])
   int qbeg[kMaxQueues + 1];  // queue x owns groups [qbeg[x], qbeg[x + 1])
   int nq;                   // number of queues (XCDs)
-  unsigned* counters;       // [x * kQueueStride] head of queue x, [kCounterBase + f] finished row items of f,
-                            // [kCounterBase + n_fft] error word
+  unsigned* counters;       // [x * kQueueStride] head of queue x, [kCounterBase + f] finished row items of f
+  unsigned* err_host;       // pinned host word, set to 1 when a bounded wait gives up
   const float2* tw;         // concatenated twiddle tables, cfg id -> offset in tw_off
   int tw_off[kNumCfg];
   int tw_cnt[kNumCfg];
   int conj;                 // 1: inverse transform
   int n_fft;
   int fenced;               // 1: agent-scope release / acquire (queues not tied to XCDs)
+  int max_spins;            // bound of a column item's wait in polls; < 0: give up every wait (tests)
 };
 
-constexpr int kMaxSpins = 1 << 24;
+constexpr int kMaxSpins = 1 << 24;  // about a second of polling
 
 // One configuration's tile as its own (flattened) function, so that every
 // register array of the pass stays in registers inside the large dispatch.
@@ -236,18 +237,18 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
         if (d.nrow_items > 0) {
           // Bounded wait: the counter always completes (see the file comment);
           // the bound only guarantees that every wave exits even if that were
-          // broken, in which case the error word is set and the item skipped.
+          // broken, in which case the host flag is set and the item skipped.
           if (threadIdx.x == 0) {
             int spins = 0;
-            s_flag = 0;
-            while (__hip_atomic_load(done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < (unsigned)d.nrow_items) {
-              __builtin_amdgcn_s_sleep(2);
-              if (++spins > kMaxSpins) {
-                atomicOr(&a.counters[kCounterBase + a.n_fft], 1u);
-                s_flag = 1;
-                break;
-              }
+            bool give_up = a.max_spins < 0;
+            while (!give_up &&
+                   __hip_atomic_load(done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < (unsigned)d.nrow_items) {
+              if (spins++ >= a.max_spins) give_up = true;
+              else __builtin_amdgcn_s_sleep(2);
             }
+            // a plain store to host memory (no PCIe atomic); the host only tests for non-zero
+            if (give_up) __hip_atomic_store(a.err_host, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            s_flag = give_up ? 1 : 0;
             if (a.fenced) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
           }
           __syncthreads();
@@ -319,6 +320,8 @@ struct BatchedPlan {
   int n_groups = 0;
   int qbeg[kMaxQueues + 1] = {};
   unsigned* d_counters = nullptr;
+  unsigned* h_err = nullptr;  // pinned, coherent: written by the kernel when a wait gives up
+  int max_spins = 0;
   float2* d_tw = nullptr;
   int tw_off[kNumCfg] = {};
   hipStream_t cap_stream = nullptr;
@@ -420,7 +423,7 @@ Schedule build_schedule(const BatchedPlan& bp, int order, int group_kib) {
 }
 
 hipError_t launch_batched(BatchedPlan* bp, int conj, int grid, hipStream_t s) {
-  const int nc = kCounterBase + (int)bp->count + 1;
+  const int nc = kCounterBase + (int)bp->count;
   hipLaunchKernelGGL(clear_counters, dim3((unsigned)std::min(64, (nc + 255) / 256)), dim3(256), 0, s, bp->d_counters, nc);
   BatchArgs a{};
   a.desc = bp->d_desc;
@@ -438,6 +441,8 @@ hipError_t launch_batched(BatchedPlan* bp, int conj, int grid, hipStream_t s) {
   a.conj = conj;
   a.n_fft = (int)bp->count;
   a.fenced = bp->fenced;
+  a.err_host = bp->h_err;
+  a.max_spins = bp->max_spins;
   hipLaunchKernelGGL(batched_kernel, dim3((unsigned)grid), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
@@ -639,8 +644,20 @@ fft2d_status create_batched(int64_t count, const int64_t* rows, const int64_t* c
     return hipfail(e, "descriptor table");
   if ((e = hipHostMalloc((void**)&bp->h_desc, (size_t)count * sizeof(BatchDesc), hipHostMallocDefault)) != hipSuccess)
     return hipfail(e, "pinned descriptor staging");
-  if ((e = hipMalloc((void**)&bp->d_counters, (size_t)(kCounterBase + count + 1) * sizeof(unsigned))) != hipSuccess)
+  if ((e = hipMalloc((void**)&bp->d_counters, (size_t)(kCounterBase + count) * sizeof(unsigned))) != hipSuccess)
     return hipfail(e, "counters");
+  if ((e = hipHostMalloc((void**)&bp->h_err, sizeof(unsigned), hipHostMallocCoherent | hipHostMallocMapped)) !=
+      hipSuccess)
+    return hipfail(e, "pinned error word");
+  *bp->h_err = 0u;
+  // Bound of a column item's wait; FFT2D_BATCH_SPIN_LIMIT (-1 ... 2^24, -1 = give up every wait) lets
+  // tests force the give-up path from the host.
+  bp->max_spins = kMaxSpins;
+  if (const char* sl = std::getenv("FFT2D_BATCH_SPIN_LIMIT")) {
+    char* end = nullptr;
+    const long v = std::strtol(sl, &end, 10);
+    if (end != sl && *end == '\0' && v >= -1 && v <= kMaxSpins) bp->max_spins = (int)v;
+  }
   for (int64_t i = 0; i < count; ++i) {
     BatchDesc& d = bp->h_desc[i];
     d.in = nullptr;
@@ -736,6 +753,11 @@ fft2d_status create_batched(int64_t count, const int64_t* rows, const int64_t* c
 
 fft2d_status exec_batched(BatchedPlan* bp, const void* const* in, void* const* out, int direction, hipStream_t s,
                           std::string* err) {
+  // A bounded wait of an earlier execution gave up: its results are incomplete.
+  if (__atomic_exchange_n(bp->h_err, 0u, __ATOMIC_ACQ_REL) != 0u) {
+    *err = "an earlier execution of this batched plan gave up waiting for row items; its outputs are incomplete";
+    return FFT2D_ERR_INCOMPLETE;
+  }
   bool changed = bp->last_in.size() != (size_t)bp->count;
   for (int64_t i = 0; i < bp->count; ++i) {
     if (!in[i] || !out[i]) {
@@ -799,6 +821,7 @@ void destroy_batched(BatchedPlan* bp) {
   if (bp->d_items) (void)hipFree(bp->d_items);
   if (bp->d_groups) (void)hipFree(bp->d_groups);
   if (bp->d_counters) (void)hipFree(bp->d_counters);
+  if (bp->h_err) (void)hipHostFree(bp->h_err);
   if (bp->d_tw) (void)hipFree(bp->d_tw);
   delete bp;
 }

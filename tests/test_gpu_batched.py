@@ -150,3 +150,33 @@ def test_batched_512_uneven_shapes(F):
         say("batched 512 sample vs oracle worst rel_l2=%.3e" % worst)
     finally:
         plan.close()
+
+
+def test_batched_gave_up_wait_is_reported(F, monkeypatch):
+    """Every column wait is told by the host to give up at once (spin limit -1):
+    the launch still drains, and the next call reports FFT2D_ERR_INCOMPLETE once."""
+    import torch
+    monkeypatch.setenv("FFT2D_TUNE", "off")
+    monkeypatch.setenv("FFT2D_BATCH_SPIN_LIMIT", "-1")
+    shapes = [(64, 64), (256, 128)]
+    say("case batched forced give-up")
+    xs = [dev(x) for x in synth.batched_grids(13, shapes)]
+    plan = F.BatchedPlan(shapes)
+    try:
+        plan(xs, F.FORWARD)
+        torch.cuda.synchronize()
+        with pytest.raises(F.Fft2dError) as e:
+            plan(xs, F.FORWARD)
+        assert e.value.status == 10
+        torch.cuda.synchronize()
+    finally:
+        plan.close()
+    monkeypatch.setenv("FFT2D_BATCH_SPIN_LIMIT", str(1 << 24))
+    plan = F.BatchedPlan(shapes)
+    try:
+        ys = plan(xs, F.FORWARD)
+        ys = plan(xs, F.FORWARD)  # no error is left over from the other plan
+        for x, y in zip(xs, ys):
+            assert rel_l2(host(y), oracle.fft2_forward(host(x))) <= TOL
+    finally:
+        plan.close()
