@@ -175,6 +175,58 @@ def time_plain(F, torch, rows, cols, steps, warmup, seed):
     return dict(wall=wall, per_pass_ms=per, x=x_h, y=y_h, roundtrip_rel_l2=rt, plan=plan.describe())
 
 
+CONFIGS = [  # (name, batch, rows, cols, seed)
+    ("64x64 forward", 1, 64, 64, 0),
+    ("1024x1024 forward", 1, 1024, 1024, 0),
+    ("4096x4096 forward", 1, 4096, 4096, 1),
+    ("8192x8192 forward", 1, 8192, 8192, 2),
+    ("16384x2048 forward", 1, 16384, 2048, 3),
+    ("1D: 4096 rows of 16384 points forward", 4096, 1, 16384, 0),
+]
+
+
+def time_configs(F, torch, iters):
+    """Forward transform of each configuration, warm (back to back) and cold
+    (a 1 GiB scratch tensor is zeroed before each iteration, outside the timed
+    events, so the 256 MB MALL holds none of the input): median, mean, min."""
+    import synth
+    stream = torch.cuda.current_stream()
+    sh = int(stream.cuda_stream)
+    scratch = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+    res = {}
+    for name, batch, rows, cols, seed in CONFIGS:
+        shape = (batch, rows, cols) if batch > 1 else (rows, cols)
+        x = torch.from_numpy(synth.complex_grid(seed, shape)).to("cuda")
+        y = torch.empty_like(x)
+        plan = F.get_plan(batch, rows, cols, x.device)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(iters)]
+        out = {}
+        npass = int(rows > 1) + int(cols > 1)  # HBM passes: a length-1 dimension needs none
+        for mode in ("warm", "cold"):
+            for _ in range(3):
+                F.fft2d_exec(plan.handle, x.data_ptr(), y.data_ptr(), F.FORWARD, sh)
+            for a, b in ev:
+                if mode == "cold":
+                    scratch.zero_()
+                a.record(stream)
+                F.fft2d_exec(plan.handle, x.data_ptr(), y.data_ptr(), F.FORWARD, sh)
+                b.record(stream)
+            torch.cuda.synchronize()
+            t = np.array([a.elapsed_time(b) for a, b in ev])
+            med = float(np.median(t))
+            pts = batch * rows * cols
+            out[mode] = {"median_ms": round(med, 5), "mean_ms": round(float(t.mean()), 5),
+                         "min_ms": round(float(t.min()), 5),
+                         "gflops": round(flops_2d(rows, cols, batch) / med / 1e6, 1),
+                         "hbm_gbps": round(npass * BYTES_PER_POINT_PER_PASS * pts / med / 1e6, 1)}
+        out["plan"] = plan.describe()
+        res[name] = out
+        del x, y
+    del scratch
+    torch.cuda.empty_cache()
+    return res
+
+
 def time_backward(F, torch, batch, rows, cols, steps, warmup, seed):
     """fft2d_backward (adjoint kernels) against fft2d_exec on the same plan and data."""
     import synth
@@ -362,6 +414,8 @@ def main():
     if not args.no_extras:
         log("bench: backward vs plain, 8 x 2048 x 2048")
         result["backward_vs_plain"] = time_backward(F, torch, 8, 2048, 2048, 20, 3, 5)
+        log("bench: forward transforms of every configuration, warm and cold")
+        result["configs"] = time_configs(F, torch, 20)
         log("bench: batched 512 shapes vs 512 plain launches")
         result["batched_vs_plain"] = time_batched(F, torch, 10, 3, 4)
 

@@ -94,6 +94,32 @@ def test_large_forward(F, shape, seed):
     _check(F, x, -1, "%dx%d fwd" % shape)
 
 
+def test_1d_batch_4096_rows_of_16384(F):
+    """rows = 1: a batch of 4096 one-dimensional length-16384 transforms (the
+    paper's single-core FFT length, Section 4), forward and inverse; 32 sampled
+    rows against the FP64 oracle one by one, all rows against Parseval."""
+    import torch
+    say("case 1D batch 4096 x 16384")
+    x = synth.complex_grid(0, (4096, 1, 16384))
+    plan = F.get_plan(4096, 1, 16384, "cuda")
+    xd = dev(x)
+    y = plan(xd, F.FORWARD)
+    z = plan(y, F.INVERSE)
+    torch.cuda.synchronize()
+    yh = host(y)
+    rng = np.random.default_rng(1)
+    worst = 0.0
+    for b in rng.choice(4096, size=32, replace=False):
+        ref = oracle.fft1d(x[b, 0], oracle.FORWARD)
+        worst = max(worst, rel_l2(yh[b, 0], ref))
+    lhs = torch.sum(torch.abs(y.to(torch.complex128)) ** 2, dim=(1, 2))
+    rhs = 16384 * torch.sum(torch.abs(xd.to(torch.complex128)) ** 2, dim=(1, 2))
+    parseval = float(torch.max(torch.abs(lhs - rhs) / rhs))
+    rt = float(torch.linalg.vector_norm(z - xd) / torch.linalg.vector_norm(xd))
+    say("1D batch 4096x16384 sampled fwd rel_l2=%.3e parseval=%.2e round trip rel_l2=%.3e" % (worst, parseval, rt))
+    assert worst <= TOL and parseval <= 1e-5 and rt <= TOL
+
+
 def test_in_place_matches_out_of_place_and_is_deterministic(F):
     import torch
     say("case in-place 512x1024")
