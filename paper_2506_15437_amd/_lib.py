@@ -15,6 +15,8 @@ from __future__ import annotations
 import ctypes
 import os
 
+import numpy as np
+
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libfft2d.so")
 
@@ -61,7 +63,7 @@ def _load():
     lib.fft2d_plan_batched.argtypes = [pp, i64, ctypes.POINTER(i64), ctypes.POINTER(i64)]
     lib.fft2d_exec.argtypes = [vp, vp, vp, ci, vp]
     lib.fft2d_exec_pass.argtypes = [vp, vp, vp, ci, ci, vp]
-    lib.fft2d_exec_batched.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ci, vp]
+    lib.fft2d_exec_batched.argtypes = [vp, vp, vp, ci, vp]
     lib.fft2d_backward.argtypes = [vp, vp, vp, ci, vp]
     lib.fft2d_destroy.argtypes = [vp]
     lib.fft2d_status_string.argtypes = [ci]
@@ -124,11 +126,21 @@ def fft2d_exec_pass(plan: int, in_ptr: int, out_ptr: int, direction: int, pass_i
     _check(lib.fft2d_exec_pass(plan, in_ptr, out_ptr, int(direction), int(pass_index), stream), "fft2d_exec_pass")
 
 
+def pointer_array(ptrs):
+    """Device pointers as a contiguous uint64 array (returned as is if it already is one),
+    the layout of the ``const void* const*`` arrays of fft2d_exec_batched."""
+    return np.ascontiguousarray(ptrs, dtype=np.uint64)
+
+
 def fft2d_exec_batched(plan: int, in_ptrs, out_ptrs, direction: int, stream: int = 0) -> None:
-    n = len(in_ptrs)
-    ia = (ctypes.c_void_p * max(n, 1))(*[int(p) for p in in_ptrs])
-    oa = (ctypes.c_void_p * max(n, 1))(*[int(p) for p in out_ptrs])
-    _check(lib.fft2d_exec_batched(plan, ia, oa, int(direction), stream), "fft2d_exec_batched")
+    """in_ptrs, out_ptrs: sequences of device pointers, or uint64 arrays from pointer_array()
+    (no per-call conversion: what a caller that replays one pointer set should pass)."""
+    ia = pointer_array(in_ptrs)
+    oa = pointer_array(out_ptrs)
+    if ia.size != oa.size:
+        raise ValueError("in_ptrs and out_ptrs differ in length")
+    _check(lib.fft2d_exec_batched(plan, ia.ctypes.data, oa.ctypes.data, int(direction), stream),
+           "fft2d_exec_batched")
 
 
 def fft2d_backward(plan: int, grad_out_ptr: int, grad_in_ptr: int, forward_direction: int, stream: int = 0) -> None:

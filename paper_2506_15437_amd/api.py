@@ -102,7 +102,14 @@ class BatchedPlan:
             self.handle = _lib.fft2d_plan_batched([r for r, _ in self.shapes], [c for _, c in self.shapes])
 
     def exec_ptrs(self, in_ptrs, out_ptrs, direction: int, stream: int) -> None:
-        _lib.fft2d_exec_batched(self.handle, in_ptrs, out_ptrs, direction, stream)
+        """in_ptrs / out_ptrs: one device pointer per planned grid, as sequences or as
+        uint64 arrays from ``pointer_array`` (no conversion per call)."""
+        ia = _lib.pointer_array(in_ptrs)
+        oa = _lib.pointer_array(out_ptrs)
+        if ia.size != len(self.shapes) or oa.size != len(self.shapes):
+            raise ValueError("expected %d input and output pointers, got %d and %d"
+                             % (len(self.shapes), ia.size, oa.size))
+        _lib.fft2d_exec_batched(self.handle, ia, oa, direction, stream)
 
     def __call__(self, xs, direction=FORWARD, outs=None):
         if len(xs) != len(self.shapes):

@@ -131,48 +131,87 @@ struct BatchArgs {
 
 constexpr int kMaxSpins = 1 << 24;  // about a second of polling
 
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ float uniform(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+}
+template <class T>
+__device__ __forceinline__ T* uniform(T* p) {
+  const uint64_t v = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+  return reinterpret_cast<T*>((uint64_t)hi << 32 | lo);
+}
+
 // One configuration's tile as its own (flattened) function, so that every
 // register array of the pass stays in registers inside the large dispatch.
+// Its arguments are plain scalars (passed in registers): a structure passed by
+// reference would make every lane write it to and read it from scratch memory.
 // Column tiles read the row items' results, so their loads are device-scope.
+// flags: bit 0 conjugates the input, bit 1 the output.
 template <class K>
-__device__ __noinline__ __attribute__((flatten)) void tile(const PassArgs& pa, int w, float2* lds, TileIO io) {
+__device__ __noinline__ __attribute__((flatten)) void tile(const float2* in, float2* out, const float2* tw, int tw_count,
+                                                           int rows, int cols, int w, int flags, float scale,
+                                                           float2* lds) {
   static_assert(K::valid() && K::THREADS == kThreads, "batched configurations use 512 threads");
+  // The arguments arrive in vector registers; they are uniform, so move them
+  // to scalar registers (keeps the address arithmetic scalar).
+  rows = uniform(rows);
+  cols = uniform(cols);
+  PassArgs pa{};
+  pa.in = uniform(in);
+  pa.out = uniform(out);
+  pa.tw = uniform(tw);
+  pa.tw_count = uniform(tw_count);
+  pa.total = (int64_t)rows * cols;
+  pa.nvec = K::COL ? cols : rows;
+  pa.ncols = cols;
+  pa.m1 = 1;
+  flags = uniform(flags);
+  TileIO io;
+  io.conj_in = (flags & 1) != 0;
+  io.conj_out = (flags & 2) != 0;
+  io.scale = uniform(scale);
+  w = uniform(w);
   fft_tile<K, -1, K::COL ? kAuxDevice : 0>(pa, w, lds, io);
 }
 
-__device__ __forceinline__ void run_tile(int cfg, const PassArgs& pa, int w, float2* lds, TileIO io) {
+#define FFT2D_TILE_ARGS in, out, tw, tw_count, rows, cols, w, flags, scale, lds
+__device__ __forceinline__ void run_tile(int cfg, const float2* in, float2* out, const float2* tw, int tw_count,
+                                         int rows, int cols, int w, int flags, float scale, float2* lds) {
   switch (cfg) {
-    case 1: tile<BR2>(pa, w, lds, io); break;
-    case 2: tile<BR4>(pa, w, lds, io); break;
-    case 3: tile<BR8>(pa, w, lds, io); break;
-    case 4: tile<BR16>(pa, w, lds, io); break;
-    case 5: tile<BR32>(pa, w, lds, io); break;
-    case 6: tile<BR64>(pa, w, lds, io); break;
-    case 7: tile<BR128>(pa, w, lds, io); break;
-    case 8: tile<BR256>(pa, w, lds, io); break;
-    case 9: tile<BR512>(pa, w, lds, io); break;
-    case 10: tile<BR1024>(pa, w, lds, io); break;
-    case 11: tile<BR2048>(pa, w, lds, io); break;
-    case 12: tile<BR4096>(pa, w, lds, io); break;
-    case 13: tile<BR8192>(pa, w, lds, io); break;
-    case 14: tile<BR16384>(pa, w, lds, io); break;
-    case 17: tile<BC2>(pa, w, lds, io); break;
-    case 18: tile<BC4>(pa, w, lds, io); break;
-    case 19: tile<BC8>(pa, w, lds, io); break;
-    case 20: tile<BC16>(pa, w, lds, io); break;
-    case 21: tile<BC32>(pa, w, lds, io); break;
-    case 22: tile<BC64>(pa, w, lds, io); break;
-    case 23: tile<BC128>(pa, w, lds, io); break;
-    case 24: tile<BC256>(pa, w, lds, io); break;
-    case 25: tile<BC512>(pa, w, lds, io); break;
-    case 26: tile<BC1024>(pa, w, lds, io); break;
-    case 27: tile<BC2048>(pa, w, lds, io); break;
-    case 28: tile<BC4096>(pa, w, lds, io); break;
-    case 29: tile<BC8192>(pa, w, lds, io); break;
-    case 30: tile<BC16384>(pa, w, lds, io); break;
+    case 1: tile<BR2>(FFT2D_TILE_ARGS); break;
+    case 2: tile<BR4>(FFT2D_TILE_ARGS); break;
+    case 3: tile<BR8>(FFT2D_TILE_ARGS); break;
+    case 4: tile<BR16>(FFT2D_TILE_ARGS); break;
+    case 5: tile<BR32>(FFT2D_TILE_ARGS); break;
+    case 6: tile<BR64>(FFT2D_TILE_ARGS); break;
+    case 7: tile<BR128>(FFT2D_TILE_ARGS); break;
+    case 8: tile<BR256>(FFT2D_TILE_ARGS); break;
+    case 9: tile<BR512>(FFT2D_TILE_ARGS); break;
+    case 10: tile<BR1024>(FFT2D_TILE_ARGS); break;
+    case 11: tile<BR2048>(FFT2D_TILE_ARGS); break;
+    case 12: tile<BR4096>(FFT2D_TILE_ARGS); break;
+    case 13: tile<BR8192>(FFT2D_TILE_ARGS); break;
+    case 14: tile<BR16384>(FFT2D_TILE_ARGS); break;
+    case 17: tile<BC2>(FFT2D_TILE_ARGS); break;
+    case 18: tile<BC4>(FFT2D_TILE_ARGS); break;
+    case 19: tile<BC8>(FFT2D_TILE_ARGS); break;
+    case 20: tile<BC16>(FFT2D_TILE_ARGS); break;
+    case 21: tile<BC32>(FFT2D_TILE_ARGS); break;
+    case 22: tile<BC64>(FFT2D_TILE_ARGS); break;
+    case 23: tile<BC128>(FFT2D_TILE_ARGS); break;
+    case 24: tile<BC256>(FFT2D_TILE_ARGS); break;
+    case 25: tile<BC512>(FFT2D_TILE_ARGS); break;
+    case 26: tile<BC1024>(FFT2D_TILE_ARGS); break;
+    case 27: tile<BC2048>(FFT2D_TILE_ARGS); break;
+    case 28: tile<BC4096>(FFT2D_TILE_ARGS); break;
+    case 29: tile<BC8192>(FFT2D_TILE_ARGS); break;
+    case 30: tile<BC16384>(FFT2D_TILE_ARGS); break;
     default: break;
   }
 }
+#undef FFT2D_TILE_ARGS
 
 __global__ void clear_counters(unsigned* c, int n) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) c[i] = 0u;
@@ -205,29 +244,18 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
       unsigned* done = &a.counters[kCounterBase + f];
       const bool inv = a.conj != 0;
       const float s = inv ? 1.0f / ((float)d.rows * (float)d.cols) : 1.0f;
-      TileIO io;
-      PassArgs pa{};
-      pa.m1 = 1;
-      pa.ncols = d.cols;
-      pa.total = (int64_t)d.rows * d.cols;
       if (kind == kCopyItem) {
         if (threadIdx.x == 0) {
-          float2 v = d.in[0];
-          if (inv) v.y = -v.y;
-          d.out[0] = make_float2(v.x * s, inv ? -v.y * s : v.y * s);
+          const float2 v = d.in[0];
+          d.out[0] = make_float2(v.x * s, v.y * s);
         }
         continue;
       }
       if (kind == kRowItem) {
-        pa.in = d.in;
-        pa.out = d.out;
-        pa.nvec = d.rows;
-        pa.tw = a.tw + a.tw_off[d.row_cfg];
-        pa.tw_count = a.tw_cnt[d.row_cfg];
-        io.conj_in = inv;
-        io.conj_out = inv && d.rows == 1;
-        io.scale = d.rows == 1 ? s : 1.0f;
-        run_tile(d.row_cfg, pa, (int)item.y, lds, io);
+        // the inverse conjugates on load; a single-row grid also conjugates and scales on store
+        const int flags = inv ? (d.rows == 1 ? 3 : 1) : 0;
+        run_tile(d.row_cfg, d.in, d.out, a.tw + a.tw_off[d.row_cfg], a.tw_cnt[d.row_cfg], d.rows, d.cols,
+                 (int)item.y, flags, d.rows == 1 ? s : 1.0f, lds);
         // publish: own stores acknowledged by the L2, workgroup joined, one increment
         if (a.fenced) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __builtin_amdgcn_s_waitcnt(0);
@@ -256,15 +284,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
           __syncthreads();
           if (timed_out) continue;
         }
-        pa.in = d.nrow_items > 0 ? d.out : d.in;
-        pa.out = d.out;
-        pa.nvec = d.cols;
-        pa.tw = a.tw + a.tw_off[d.col_cfg];
-        pa.tw_count = a.tw_cnt[d.col_cfg];
-        io.conj_in = inv && d.nrow_items == 0;
-        io.conj_out = inv;
-        io.scale = s;
-        run_tile(d.col_cfg, pa, (int)item.y, lds, io);
+        // without a row pass (cols == 1) the column item reads the input and conjugates it itself
+        const int flags = inv ? (d.nrow_items > 0 ? 2 : 3) : 0;
+        run_tile(d.col_cfg, d.nrow_items > 0 ? d.out : d.in, d.out, a.tw + a.tw_off[d.col_cfg],
+                 a.tw_cnt[d.col_cfg], d.rows, d.cols, (int)item.y, flags, s, lds);
       }
       __syncthreads();  // the LDS of this item is free before the next item starts
     }
