@@ -59,8 +59,11 @@ int64_t choose_split(int64_t rows, int64_t cols) {
     return usable(m1) ? m1 : 1;
   }
   if (rows * cols < (int64_t(1) << 22) || cols > 8192) return 1;
-  const int64_t m1 = 16384 / cols;
-  return usable(m1) ? m1 : 1;
+  // M1 rows of the combine fill one workgroup (16384 points; 32768 for
+  // cols = 8192, where M1 = 2 would leave 4096-long, 64-byte-wide columns).
+  const int64_t m1 = cols == 8192 ? 4 : 16384 / cols;
+  if (usable(m1)) return m1;
+  return usable(16384 / cols) ? 16384 / cols : 1;
 }
 
 }  // namespace

@@ -10,8 +10,10 @@ using namespace dev;
 namespace {
 
 // Row passes with an M1-point combine (split column transforms): M1 rows of
-// length L per workgroup, 128 KiB of data, 512 threads, 68 KiB of LDS.
+// length L per workgroup, 128 KiB of data, 512 threads, 68 KiB of LDS (and
+// one 256 KiB variant of 1024 threads for L = 8192).
 using RC8192x2 = Cfg<8192, 32, 2, 2, false, 16, 16, 32>;
+using RC8192x4 = Cfg<8192, 32, 4, 2, false, 16, 16, 32>;
 using RC4096x4 = Cfg<4096, 32, 4, 2, false, 16, 16, 16>;
 using RC2048x8 = Cfg<2048, 32, 8, 2, false, 16, 16, 8>;
 using RC1024x16 = Cfg<1024, 32, 16, 2, false, 16, 16, 4>;
@@ -23,7 +25,8 @@ using S2048 = Cfg<2048, 32, 16, 2, true, 16, 16, 8>;
 using S4096 = Cfg<4096, 32, 8, 2, true, 16, 16, 16>;
 
 const PassKernel kCombineKernels[] = {
-    describe<RC8192x2, true, 4>(), describe<RC4096x4, true, 4>(), describe<RC2048x8, true, 4>(),
+    describe<RC8192x2, true, 4>(), describe<RC8192x4, true, 1>(), describe<RC4096x4, true, 4>(),
+    describe<RC2048x8, true, 4>(),
     describe<RC1024x16, true, 4>(),
 };
 const PassKernel kSplitColKernels[] = {

@@ -172,7 +172,8 @@ def test_abi_errors_on_device_pointers(F):
 # Split column transforms (row pass with an M1-point combine + column pass of
 # length rows/M1), forced at sizes the oracle handles in well under a second.
 SPLIT_CASES = [(1, (32, 1024), 16), (2, (64, 1024), 16), (1, (256, 2048), 8), (3, (64, 2048), 8),
-               (1, (512, 4096), 4), (2, (128, 4096), 4), (1, (64, 8192), 2), (1, (2048, 1024), 16),
+               (1, (512, 4096), 4), (2, (128, 4096), 4), (1, (64, 8192), 2), (1, (64, 8192), 4),
+               (2, (32, 8192), 4), (1, (2048, 1024), 16),
                (1, (8192, 2048), 8)]
 
 
@@ -211,9 +212,12 @@ def test_auto_split_choice(F):
     assert os.environ.get("FFT2D_SPLIT") is None
     p = F.Plan(1, 4096, 4096)
     q = F.Plan(1, 64, 64)
+    r = F.Plan(1, 8192, 8192)
     try:
         assert "split=4 " in p.describe(), p.describe()
         assert "split=1 " in q.describe(), q.describe()
+        assert "split=4 " in r.describe(), r.describe()
     finally:
         p.close()
         q.close()
+        r.close()
