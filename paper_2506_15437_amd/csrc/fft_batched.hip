@@ -114,7 +114,7 @@ constexpr int kXccIdReg = (3 << 11) | 20;            // hwreg(HW_REG_XCC_ID, 0, 
 
 struct BatchArgs {
   const BatchDesc* desc;
-  const uint2* items;       // x = fft << 2 | kind, y = tile index
+  const uint2* items;       // x = fft << 2 | kind, y = first tile | tile count << 16
   const uint32_t* groups;   // group g covers items [groups[g], groups[g + 1])
   int qbeg[kMaxQueues + 1];  // queue x owns groups [qbeg[x], qbeg[x + 1])
   int nq;                   // number of queues (XCDs)
@@ -148,11 +148,13 @@ __device__ __forceinline__ T* uniform(T* p) {
 // Its arguments are plain scalars (passed in registers): a structure passed by
 // reference would make every lane write it to and read it from scratch memory.
 // Column tiles read the row items' results, so their loads are device-scope.
+// A call runs the tiles t0 .. t0 + cnt - 1 of one grid, so the cost of the
+// call (saving the registers the callee must preserve) is paid once per run.
 // flags: bit 0 conjugates the input, bit 1 the output.
 template <class K>
 __device__ __noinline__ __attribute__((flatten)) void tile(const float2* in, float2* out, const float2* tw, int tw_count,
-                                                           int rows, int cols, int w, int flags, float scale,
-                                                           float2* lds) {
+                                                           int rows, int cols, int t0, int cnt, int flags,
+                                                           float scale, float2* lds) {
   static_assert(K::valid() && K::THREADS == kThreads, "batched configurations use 512 threads");
   // The arguments arrive in vector registers; they are uniform, so move them
   // to scalar registers (keeps the address arithmetic scalar).
@@ -172,13 +174,17 @@ __device__ __noinline__ __attribute__((flatten)) void tile(const float2* in, flo
   io.conj_in = (flags & 1) != 0;
   io.conj_out = (flags & 2) != 0;
   io.scale = uniform(scale);
-  w = uniform(w);
-  fft_tile<K, -1, K::COL ? kAuxDevice : 0>(pa, w, lds, io);
+  t0 = uniform(t0);
+  cnt = uniform(cnt);
+  for (int i = 0; i < cnt; ++i) {
+    if (i > 0) __syncthreads();  // the previous tile's LDS reads are done
+    fft_tile<K, -1, K::COL ? kAuxDevice : 0>(pa, t0 + i, lds, io);
+  }
 }
 
-#define FFT2D_TILE_ARGS in, out, tw, tw_count, rows, cols, w, flags, scale, lds
+#define FFT2D_TILE_ARGS in, out, tw, tw_count, rows, cols, t0, cnt, flags, scale, lds
 __device__ __forceinline__ void run_tile(int cfg, const float2* in, float2* out, const float2* tw, int tw_count,
-                                         int rows, int cols, int w, int flags, float scale, float2* lds) {
+                                         int rows, int cols, int t0, int cnt, int flags, float scale, float2* lds) {
   switch (cfg) {
     case 1: tile<BR2>(FFT2D_TILE_ARGS); break;
     case 2: tile<BR4>(FFT2D_TILE_ARGS); break;
@@ -240,6 +246,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
       const uint2 item = a.items[it];
       const int f = (int)(item.x >> 2);
       const int kind = (int)(item.x & 3u);
+      const int t0 = (int)(item.y & 0xffffu);  // first tile of the run
+      const int cnt = (int)(item.y >> 16);     // tiles in the run
       const BatchDesc d = a.desc[f];
       unsigned* done = &a.counters[kCounterBase + f];
       const bool inv = a.conj != 0;
@@ -255,12 +263,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
         // the inverse conjugates on load; a single-row grid also conjugates and scales on store
         const int flags = inv ? (d.rows == 1 ? 3 : 1) : 0;
         run_tile(d.row_cfg, d.in, d.out, a.tw + a.tw_off[d.row_cfg], a.tw_cnt[d.row_cfg], d.rows, d.cols,
-                 (int)item.y, flags, d.rows == 1 ? s : 1.0f, lds);
+                 t0, cnt, flags, d.rows == 1 ? s : 1.0f, lds);
         // publish: own stores acknowledged by the L2, workgroup joined, one increment
         if (a.fenced) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
-        if (threadIdx.x == 0) __hip_atomic_fetch_add(done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (threadIdx.x == 0) __hip_atomic_fetch_add(done, (unsigned)cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       } else {
         if (d.nrow_items > 0) {
           // Bounded wait: the counter always completes (see the file comment);
@@ -287,7 +295,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
         // without a row pass (cols == 1) the column item reads the input and conjugates it itself
         const int flags = inv ? (d.nrow_items > 0 ? 2 : 3) : 0;
         run_tile(d.col_cfg, d.nrow_items > 0 ? d.out : d.in, d.out, a.tw + a.tw_off[d.col_cfg],
-                 a.tw_cnt[d.col_cfg], d.rows, d.cols, (int)item.y, flags, s, lds);
+                 a.tw_cnt[d.col_cfg], d.rows, d.cols, t0, cnt, flags, s, lds);
       }
       __syncthreads();  // the LDS of this item is free before the next item starts
     }
@@ -363,24 +371,26 @@ struct Schedule {
   int qbeg[kMaxQueues + 1] = {};
 };
 
-// Points one item moves (its data size / 8 bytes).
-int64_t item_points(const BatchedPlan& bp, const PassKernel* tab, int f, int kind, int t) {
+// Points one item moves (its data size / 8 bytes): tiles t0 .. t0 + cnt - 1.
+int64_t item_points(const BatchedPlan& bp, const PassKernel* tab, int f, int kind, int t0, int cnt) {
   const int64_t M = bp.rows[(size_t)f], N = bp.cols[(size_t)f];
   if (kind == kCopyItem) return 1;
   if (kind == kRowItem) {
     const int64_t C = tab[bp.row_cfg[(size_t)f]].C;
-    return std::min<int64_t>(C, M - (int64_t)t * C) * N;
+    return std::min<int64_t>(C * cnt, M - (int64_t)t0 * C) * N;
   }
   const int64_t C = tab[bp.col_cfg[(size_t)f]].C;
-  return std::min<int64_t>(C, N - (int64_t)t * C) * M;
+  return std::min<int64_t>(C * cnt, N - (int64_t)t0 * C) * M;
 }
 
 // Build the queues. Transforms go to the XCD with the least assigned points
 // (largest first). Within a queue, order 0 lists every row item and then every
 // column item (largest transforms first); order 1 works in chunks of about
 // 16 MiB per queue: a chunk's row items, then the previous chunk's column
-// items (which then mostly read data still in the MALL). Consecutive items
-// form groups of at least group_kib KiB of data; a workgroup pops one group.
+// items (which then mostly read data still in the MALL). An item is a run of
+// consecutive tiles of one grid and kind, of about group_kib KiB of data;
+// consecutive items form groups of at least that size; a workgroup pops one
+// group.
 Schedule build_schedule(const BatchedPlan& bp, int order, int group_kib) {
   const PassKernel* tab = cfg_table();
   std::vector<int> idx((size_t)bp.count);
@@ -395,17 +405,22 @@ Schedule build_schedule(const BatchedPlan& bp, int order, int group_kib) {
     load[x] += pts(f);
   }
   Schedule sc;
+  const int64_t target = (int64_t)group_kib * 1024 / 8;
+  // runs of tiles: about `target` points each (at least one tile); counts < 2^16
+  auto runs = [&](int f, int kind, int ntiles, std::vector<uint2>& out) {
+    const int64_t per_tile = std::max<int64_t>(1, item_points(bp, tab, f, kind, 0, 1));
+    const int run = (int)std::max<int64_t>(1, std::min<int64_t>(target / per_tile, 0xffff));
+    for (int t = 0; t < ntiles; t += run)
+      out.push_back(make_uint2((unsigned)f << 2 | (unsigned)kind, (unsigned)t | (unsigned)std::min(run, ntiles - t) << 16));
+  };
   auto rows_of = [&](int f, std::vector<uint2>& out) {
     if (bp.rows[(size_t)f] == 1 && bp.cols[(size_t)f] == 1) {
-      out.push_back(make_uint2((unsigned)f << 2 | kCopyItem, 0));
+      out.push_back(make_uint2((unsigned)f << 2 | kCopyItem, 1u << 16));
       return;
     }
-    for (int t = 0; t < bp.nrow[(size_t)f]; ++t) out.push_back(make_uint2((unsigned)f << 2 | kRowItem, (unsigned)t));
+    runs(f, kRowItem, bp.nrow[(size_t)f], out);
   };
-  auto cols_of = [&](int f, std::vector<uint2>& out) {
-    for (int t = 0; t < bp.ncol[(size_t)f]; ++t) out.push_back(make_uint2((unsigned)f << 2 | kColItem, (unsigned)t));
-  };
-  const int64_t target = (int64_t)group_kib * 1024 / 8;
+  auto cols_of = [&](int f, std::vector<uint2>& out) { runs(f, kColItem, bp.ncol[(size_t)f], out); };
   for (int x = 0; x < bp.nq; ++x) {
     std::vector<uint2> items;
     if (order == 0) {
@@ -436,7 +451,7 @@ Schedule build_schedule(const BatchedPlan& bp, int order, int group_kib) {
         sc.groups.push_back((uint32_t)sc.items.size());
         acc = 0;
       }
-      acc += item_points(bp, tab, (int)(it.x >> 2), (int)(it.x & 3u), (int)it.y);
+      acc += item_points(bp, tab, (int)(it.x >> 2), (int)(it.x & 3u), (int)(it.y & 0xffffu), (int)(it.y >> 16));
       sc.items.push_back(it);
     }
   }
