@@ -227,6 +227,87 @@ def time_configs(F, torch, iters):
     return res
 
 
+def device_copy_gbps(torch, rows, cols, iters=20):
+    """Read+write bandwidth of a plain device copy of one rows x cols complex64
+    grid (torch's copy kernel), warm (source and destination stay in the 256 MB
+    MALL) and cold (1 GiB scrubbed before each copy)."""
+    x = torch.zeros((rows, cols), dtype=torch.complex64, device="cuda")
+    y = torch.empty_like(x)
+    scratch = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+    out = {}
+    for mode in ("warm", "cold"):
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(iters)]
+        for _ in range(3):
+            y.copy_(x)
+        for a, b in ev:
+            if mode == "cold":
+                scratch.zero_()
+            a.record(stream)
+            y.copy_(x)
+            b.record(stream)
+        torch.cuda.synchronize()
+        med = float(np.median([a.elapsed_time(b) for a, b in ev]))
+        out[mode + "_gbps"] = round(2 * x.numel() * 8 / med / 1e6, 1)
+    del x, y, scratch
+    torch.cuda.empty_cache()
+    return out
+
+
+def energy(F, torch, rows, cols, seconds):
+    """Energy of forward rows x cols transforms from the GPU's energy counter
+    (amdsmi, whole board), over a loop of about `seconds`. None when the
+    counter cannot be read."""
+    try:
+        import amdsmi
+        amdsmi.amdsmi_init()
+        h = amdsmi.amdsmi_get_processor_handles()[0]
+    except Exception as e:  # no counter on this machine: report nothing
+        log("bench: energy counter unavailable (%s)" % e)
+        return None
+
+    def joules():
+        c = amdsmi.amdsmi_get_energy_count(h)
+        return c["energy_accumulator"] * c["counter_resolution"] * 1e-6
+
+    try:
+        import synth
+        x = torch.from_numpy(synth.complex_grid(0, (rows, cols))).to("cuda")
+        y = torch.empty_like(x)
+        plan = F.get_plan(1, rows, cols, x.device)
+        sh = int(torch.cuda.current_stream().cuda_stream)
+
+        def run(n):
+            for _ in range(n):
+                F.fft2d_exec(plan.handle, x.data_ptr(), y.data_ptr(), F.FORWARD, sh)
+
+        run(20)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run(200)
+        torch.cuda.synchronize()
+        per = (time.perf_counter() - t0) / 200
+        n = max(200, int(seconds / per))
+        e0, t0 = joules(), time.perf_counter()
+        run(n)
+        torch.cuda.synchronize()
+        e1, t1 = joules(), time.perf_counter()
+        busy_w = (e1 - e0) / (t1 - t0)
+        return {"workload": "%dx%d forward, %d back-to-back transforms" % (rows, cols, n),
+                "seconds": round(t1 - t0, 3), "ms_per_transform": round((t1 - t0) / n * 1e3, 5),
+                "avg_power_w": round(busy_w, 1),
+                "energy_per_transform_j": (e1 - e0) / n,
+                "source": "amdsmi energy counter (whole GPU)"}
+    except Exception as e:
+        log("bench: energy measurement failed (%s)" % e)
+        return None
+    finally:
+        try:
+            amdsmi.amdsmi_shut_down()
+        except Exception:
+            pass
+
+
 def time_backward(F, torch, batch, rows, cols, steps, warmup, seed):
     """fft2d_backward (adjoint kernels) against fft2d_exec on the same plan and data."""
     import synth
@@ -308,22 +389,23 @@ def time_batched(F, torch, steps, warmup, seed):
     return res
 
 
-def cpu_baseline(rows, cols, x, budget_s, max_reps):
-    """The FP64 oracle (plain recursive radix-2, OpenMP) on the same input."""
+def cpu_baseline(rows, cols, x, budget_s, max_reps, threads=0):
+    """The FP64 oracle (plain recursive radix-2, OpenMP) on the same input;
+    threads = 0 uses every host core."""
     import oracle
-    threads = oracle.max_threads()
+    used = threads if threads > 0 else oracle.max_threads()
     reps = 0
     t0 = time.perf_counter()
     ref = None
     while reps < max_reps:
-        ref = oracle.fft2_forward(x)
-        oracle.ifft2(ref)
+        ref = oracle.fft2_forward(x, threads)
+        oracle.ifft2(ref, threads)
         reps += 1
         if time.perf_counter() - t0 >= budget_s:
             break
     dt = time.perf_counter() - t0
     gflops = 2 * flops_2d(rows, cols) * reps / dt / 1e9
-    return ref, {"value": gflops, "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
+    return ref, {"value": gflops, "unit": "GFLOP/s", "cores": used, "kind": "oracle",
                  "sample": "%d forward+inverse round trips of the %dx%d grid, FP64 recursive radix-2 with OpenMP "
                            "over rows then columns, %.1f s" % (reps, rows, cols, dt)}
 
@@ -417,6 +499,10 @@ def main():
         result["backward_vs_plain"] = time_backward(F, torch, 8, 2048, 2048, 20, 3, 5)
         log("bench: forward transforms of every configuration, warm and cold")
         result["configs"] = time_configs(F, torch, 20)
+        log("bench: device copy bandwidth, 4096 x 4096 complex64")
+        result["device_copy"] = device_copy_gbps(torch, rows, cols)
+        log("bench: energy per transform (1024 x 1024 and 4096 x 4096)")
+        result["energy"] = [energy(F, torch, 1024, 1024, 1.5), energy(F, torch, 4096, 4096, 1.5)]
         log("bench: batched 512 shapes vs 512 plain launches")
         result["batched_vs_plain"] = time_batched(F, torch, 10, 3, 4)
 
@@ -424,6 +510,9 @@ def main():
         log("bench: CPU baseline (FP64 oracle)")
         ref, cpu = cpu_baseline(rows, cols, r["x"], args.cpu_budget, 200)
         result["cpu_baseline"] = cpu
+        log("bench: CPU baseline on one core")
+        _, cpu1 = cpu_baseline(rows, cols, r["x"], 4.0, 50, threads=1)
+        result["cpu_baseline_1core"] = cpu1
         num = np.linalg.norm((r["y"].astype(np.complex128) - ref).ravel())
         result["fwd_rel_l2_vs_oracle"] = float(num / np.linalg.norm(ref.ravel()))
 
