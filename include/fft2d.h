@@ -20,8 +20,12 @@
  * [1, 16384] per dimension.
  *
  * Streams: `stream` is a hipStream_t passed as void* (NULL = the default
- * stream). Every exec/backward call only enqueues work on that stream; it never
- * synchronises and never allocates, so it can be captured in a HIP graph.
+ * stream). fft2d_exec, fft2d_exec_pass and fft2d_backward only enqueue work on
+ * that stream; they never synchronise and never allocate, so they can be
+ * captured in a HIP graph. fft2d_exec_batched enqueues the plan's own
+ * instantiated graph; when the pointer set changed it first waits on the host
+ * for the previous descriptor upload (from pinned memory) to finish, so it is
+ * not meant to be captured.
  *
  * Errors: every function returns an fft2d_status and never throws. On failure
  * nothing is enqueued, outputs are untouched, and fft2d_last_error() gives a
@@ -31,7 +35,7 @@
  * used from several host threads and streams at once. A split plan (large
  * grids; see fft2d_plan) and a batched plan own mutable device memory (work
  * buffer; work counters and descriptor table): use each from one stream at a
- * time.
+ * time, and a batched plan from one host thread at a time.
  */
 #ifndef FFT2D_H
 #define FFT2D_H
@@ -69,7 +73,8 @@ typedef struct fft2d_plan_s* fft2d_plan_t;
 /*
  * fft2d_plan -- create a plan for `batch` independent rows x cols transforms.
  *   out    : receives the handle (set to NULL on failure).
- *   batch  : number of grids, >= 1; grids are contiguous, rows*cols points apart.
+ *   batch  : number of grids, >= 1; grids are contiguous, rows*cols points apart;
+ *            batch*rows*cols <= 2^35 points (256 GiB), else FFT2D_ERR_INVALID_SIZE.
  *   rows   : M, power of two in [1, 16384] (rows = 1 gives a batch of 1D FFTs).
  *   cols   : N, power of two in [1, 16384], the contiguous dimension.
  * Builds the FP32 twiddle tables (each entry computed in FP64 from its own
@@ -89,9 +94,16 @@ fft2d_status fft2d_plan(fft2d_plan_t* out, int64_t batch, int64_t rows, int64_t 
  * fft2d_plan_batched -- plan `count` independent transforms of different shapes
  * (rows[i] x cols[i], powers of two in [1, 16384]), executed by
  * fft2d_exec_batched in one persistent kernel launch replayed from a HIP graph.
- * rows and cols are host arrays of `count` entries, read during the call only.
- * Radix schedule, tile shape and persistent grid size come from the library's
- * autotuner (a cached choice per shape class when one exists).
+ * rows and cols are host arrays of `count` entries (1 <= count <= 2^24), read
+ * during the call only. Radix schedule and tile shape are fixed per length;
+ * the persistent grid size, the item order and the work-group granularity come
+ * from the library's autotuner, cached per shape set in a text file
+ * (FFT2D_TUNE=off|cached|full, FFT2D_TUNE_CACHE=<path>, default
+ * $HOME/.cache/fft2d_tune.txt). Tuning runs the kernel on two temporary device
+ * buffers of the plan's total size, freed before the call returns; if they
+ * cannot be allocated the call fails with FFT2D_ERR_OUT_OF_MEMORY (FFT2D_TUNE=off
+ * avoids them). The plan also launches a small probe kernel once to learn
+ * which XCD each workgroup runs on.
  */
 fft2d_status fft2d_plan_batched(fft2d_plan_t* out, int64_t count, const int64_t* rows, const int64_t* cols);
 

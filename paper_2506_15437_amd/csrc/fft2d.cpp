@@ -269,7 +269,9 @@ fft2d_status fft2d_plan(fft2d_plan_t* out, int64_t batch, int64_t rows, int64_t 
   if (!pow2_in_range(rows) || !pow2_in_range(cols))
     return fail(FFT2D_ERR_INVALID_SIZE, "rows and cols must be powers of two in [1, 16384], got " +
                                             std::to_string(rows) + "x" + std::to_string(cols));
-  if (batch > (int64_t(1) << 40) / (rows * cols)) return fail(FFT2D_ERR_INVALID_SIZE, "batch*rows*cols too large");
+  // 2^35 points (256 GiB of complex64) bound every grid-size computation well inside 32 bits
+  if (batch > (int64_t(1) << 35) / (rows * cols))
+    return fail(FFT2D_ERR_INVALID_SIZE, "batch*rows*cols exceeds 2^35 points");
   fft2d_plan_s* p = new (std::nothrow) fft2d_plan_s();
   if (!p) return fail(FFT2D_ERR_OUT_OF_MEMORY, "host allocation failed");
   p->kind = kUniform;

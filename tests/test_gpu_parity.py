@@ -120,6 +120,37 @@ def test_1d_batch_4096_rows_of_16384(F):
     assert worst <= TOL and parseval <= 1e-5 and rt <= TOL
 
 
+@pytest.mark.parametrize("shape", [(256, 512), (4096, 1024)], ids=["256x512", "4096x1024-split"])
+def test_exec_captured_in_hip_graph(F, shape):
+    """fft2d_exec enqueues kernels only, so it can be captured in a HIP graph
+    (torch.cuda.CUDAGraph); every replay, with eager work between replays,
+    equals the eager result bit for bit."""
+    import torch
+    say("case HIP graph capture %dx%d" % shape)
+    x = dev(synth.complex_grid(31, shape))
+    y = torch.empty_like(x)
+    plan = F.get_plan(1, shape[0], shape[1], "cuda")
+    eager = plan(x, F.FORWARD)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            plan.exec_ptr(x.data_ptr(), y.data_ptr(), F.FORWARD, torch.cuda.current_stream().cuda_stream)
+    torch.cuda.current_stream().wait_stream(s)
+    for rep in range(3):
+        y.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(y, eager), rep
+        other = plan(x, F.INVERSE)  # eager work between replays
+        torch.cuda.synchronize()
+        del other
+    assert rel_l2(host(y), oracle.fft2_forward(host(x))) <= TOL
+    del g
+
+
 def test_in_place_matches_out_of_place_and_is_deterministic(F):
     import torch
     say("case in-place 512x1024")
