@@ -117,8 +117,8 @@ def test_batched_rejects_bad_input(F, monkeypatch):
 def test_batched_512_uneven_shapes(F):
     """512 transforms of 2^a x 2^b, a, b in [6, 11] drawn from seed 4, one persistent launch.
 
-    Every output is checked against the plain path (fft2d_exec of the same shape)
-    on the GPU, a sample of 24 against the FP64 oracle, and all against Parseval."""
+    Every output is checked against the FP64 oracle, against the plain path
+    (fft2d_exec of the same shape) on the GPU, and against Parseval."""
     import torch
     shapes = synth.pow2_shapes(4, 512)
     say("case batched 512 shapes, %d points" % sum(r * c for r, c in shapes))
@@ -141,13 +141,12 @@ def test_batched_512_uneven_shapes(F):
             assert abs(lhs - rhs) <= 1e-5 * rhs
         say("batched 512 vs plain path worst rel_l2=%.3e" % worst_plain)
         assert worst_plain <= 2 * TOL
-        rng = np.random.default_rng(0)
         worst = 0.0
-        for i in rng.choice(len(shapes), size=24, replace=False):
+        for i in range(len(shapes)):
             e = rel_l2(host(ys[i]), oracle.fft2_forward(xs[i]))
             worst = max(worst, e)
             assert e <= TOL, (i, shapes[i], e)
-        say("batched 512 sample vs oracle worst rel_l2=%.3e" % worst)
+        say("batched 512 all vs oracle worst rel_l2=%.3e" % worst)
     finally:
         plan.close()
 
