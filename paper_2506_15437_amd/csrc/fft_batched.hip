@@ -52,7 +52,7 @@ namespace {
 using namespace dev;
 
 constexpr int kThreads = 512;
-constexpr int kNumCfg = 32;  // id = mode * 16 + log2(L); mode 0 = row, 1 = column
+constexpr int kNumCfg = 48;  // id = mode * 16 + log2(L); mode 0 = row, 1 = column, 2 = row with combine
 
 // Row configurations (512 threads each).
 using BR2 = Cfg<2, 2, 512, 1, false, 2>;
@@ -84,6 +84,13 @@ using BC2048 = Cfg<2048, 32, 8, 2, true, 16, 16, 8>;
 using BC4096 = Cfg<4096, 32, 4, 2, true, 16, 16, 16>;
 using BC8192 = Cfg<8192, 32, 2, 2, true, 16, 16, 32>;
 using BC16384 = Cfg<16384, 32, 1, 2, true, 16, 16, 16, 4>;
+// Row-with-combine configurations of split transforms (512 threads each): M1
+// rows of length L per tile, M1 = C.
+using BRC512 = Cfg<512, 16, 16, 1, false, 16, 16, 2>;
+using BRC1024 = Cfg<1024, 32, 16, 2, false, 16, 16, 4>;
+using BRC2048 = Cfg<2048, 32, 8, 2, false, 16, 16, 8>;
+using BRC4096 = Cfg<4096, 32, 4, 2, false, 16, 16, 16>;
+using BRC8192 = Cfg<8192, 32, 2, 2, false, 16, 16, 32>;
 
 template <class... Ks>
 constexpr int max_lds() {
@@ -93,15 +100,19 @@ constexpr int max_lds() {
 }
 constexpr int kLdsElems = max_lds<BR2, BR4, BR8, BR16, BR32, BR64, BR128, BR256, BR512, BR1024, BR2048, BR4096,
                                   BR8192, BR16384, BC2, BC4, BC8, BC16, BC32, BC64, BC128, BC256, BC512, BC1024,
-                                  BC2048, BC4096, BC8192, BC16384>();
+                                  BC2048, BC4096, BC8192, BC16384, BRC512, BRC1024, BRC2048, BRC4096,
+                                  BRC8192>();
 static_assert(kLdsElems * 8 <= 80 * 1024, "two batched workgroups must fit one CU's LDS");
 
 struct BatchDesc {
   const float2* in;
   float2* out;
+  float2* work;  // split transforms: the grid between the row pass with combine and the column pass
   int32_t rows, cols;
   int32_t row_cfg, col_cfg;
   int32_t nrow_items;
+  int32_t m1;       // 1: plain; > 1: split transform, rows = m1 * m2, row items combine m1 rows
+  int32_t twc_off;  // split transforms: offset of W_rows^j, j < rows, in the twiddle buffer
   int32_t pad;
 };
 
@@ -153,22 +164,24 @@ __device__ __forceinline__ T* uniform(T* p) {
 // flags: bit 0 conjugates the input, bit 1 the output.
 template <class K>
 __device__ __noinline__ __attribute__((flatten)) void tile(const float2* in, float2* out, const float2* tw, int tw_count,
-                                                           int rows, int cols, int t0, int cnt, int flags,
+                                                           int rows, int cols, int m1, int t0, int cnt, int flags,
                                                            float scale, float2* lds) {
   static_assert(K::valid() && K::THREADS == kThreads, "batched configurations use 512 threads");
   // The arguments arrive in vector registers; they are uniform, so move them
   // to scalar registers (keeps the address arithmetic scalar).
   rows = uniform(rows);
   cols = uniform(cols);
+  m1 = uniform(m1);
   PassArgs pa{};
   pa.in = uniform(in);
   pa.out = uniform(out);
   pa.tw = uniform(tw);
   pa.tw_count = uniform(tw_count);
   pa.total = (int64_t)rows * cols;
-  pa.nvec = K::COL ? cols : rows;
+  // column tiles of a split transform: length rows / m1, m1 row blocks of cols vectors
+  pa.nvec = K::COL ? (int64_t)m1 * cols : rows;
   pa.ncols = cols;
-  pa.m1 = 1;
+  pa.m1 = m1;
   flags = uniform(flags);
   TileIO io;
   io.conj_in = (flags & 1) != 0;
@@ -182,9 +195,54 @@ __device__ __noinline__ __attribute__((flatten)) void tile(const float2* in, flo
   }
 }
 
-#define FFT2D_TILE_ARGS in, out, tw, tw_count, rows, cols, t0, cnt, flags, scale, lds
+// Tiles t0 .. t0 + cnt - 1 (tile = m2 index) of the row pass with combine of a
+// split transform: in -> work, conjugating the input for the inverse.
+template <class K>
+__device__ __noinline__ __attribute__((flatten)) void ctile(const float2* in, float2* work, const float2* tw,
+                                                            int tw_count, const float2* twc, int rows, int cols,
+                                                            int t0, int cnt, int flags, float2* lds) {
+  static_assert(K::valid() && K::THREADS == kThreads && !K::COL, "batched configurations use 512 threads");
+  rows = uniform(rows);
+  cols = uniform(cols);
+  PassArgs pa{};
+  pa.in = uniform(in);
+  pa.out = uniform(work);
+  pa.tw = uniform(tw);
+  pa.tw_count = uniform(tw_count);
+  pa.twc = uniform(twc);
+  pa.total = (int64_t)rows * cols;
+  pa.nvec = rows;
+  pa.ncols = cols;
+  pa.m1 = K::C;
+  pa.m2 = rows / K::C;
+  flags = uniform(flags);
+  TileIO io;
+  io.conj_in = (flags & 1) != 0;
+  t0 = uniform(t0);
+  cnt = uniform(cnt);
+  for (int i = 0; i < cnt; ++i) {
+    if (i > 0) __syncthreads();  // the previous tile's LDS reads are done
+    rowc_tile<K, -1, kAuxNontemporal>(pa, t0 + i, lds, io);
+  }
+}
+
+__device__ __forceinline__ void run_ctile(int cfg, const float2* in, float2* work, const float2* tw, int tw_count,
+                                          const float2* twc, int rows, int cols, int t0, int cnt, int flags,
+                                          float2* lds) {
+  switch (cfg) {
+    case 41: ctile<BRC512>(in, work, tw, tw_count, twc, rows, cols, t0, cnt, flags, lds); break;
+    case 42: ctile<BRC1024>(in, work, tw, tw_count, twc, rows, cols, t0, cnt, flags, lds); break;
+    case 43: ctile<BRC2048>(in, work, tw, tw_count, twc, rows, cols, t0, cnt, flags, lds); break;
+    case 44: ctile<BRC4096>(in, work, tw, tw_count, twc, rows, cols, t0, cnt, flags, lds); break;
+    case 45: ctile<BRC8192>(in, work, tw, tw_count, twc, rows, cols, t0, cnt, flags, lds); break;
+    default: break;
+  }
+}
+
+#define FFT2D_TILE_ARGS in, out, tw, tw_count, rows, cols, m1, t0, cnt, flags, scale, lds
 __device__ __forceinline__ void run_tile(int cfg, const float2* in, float2* out, const float2* tw, int tw_count,
-                                         int rows, int cols, int t0, int cnt, int flags, float scale, float2* lds) {
+                                         int rows, int cols, int m1, int t0, int cnt, int flags, float scale,
+                                         float2* lds) {
   switch (cfg) {
     case 1: tile<BR2>(FFT2D_TILE_ARGS); break;
     case 2: tile<BR4>(FFT2D_TILE_ARGS); break;
@@ -262,8 +320,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
       if (kind == kRowItem) {
         // the inverse conjugates on load; a single-row grid also conjugates and scales on store
         const int flags = inv ? (d.rows == 1 ? 3 : 1) : 0;
-        run_tile(d.row_cfg, d.in, d.out, a.tw + a.tw_off[d.row_cfg], a.tw_cnt[d.row_cfg], d.rows, d.cols,
-                 t0, cnt, flags, d.rows == 1 ? s : 1.0f, lds);
+        if (d.m1 > 1)
+          run_ctile(d.row_cfg, d.in, d.work, a.tw + a.tw_off[d.row_cfg], a.tw_cnt[d.row_cfg], a.tw + d.twc_off,
+                    d.rows, d.cols, t0, cnt, flags, lds);
+        else
+          run_tile(d.row_cfg, d.in, d.out, a.tw + a.tw_off[d.row_cfg], a.tw_cnt[d.row_cfg], d.rows, d.cols, 1,
+                   t0, cnt, flags, d.rows == 1 ? s : 1.0f, lds);
         // publish: own stores acknowledged by the L2, workgroup joined, one increment
         if (a.fenced) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __builtin_amdgcn_s_waitcnt(0);
@@ -294,8 +356,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
         }
         // without a row pass (cols == 1) the column item reads the input and conjugates it itself
         const int flags = inv ? (d.nrow_items > 0 ? 2 : 3) : 0;
-        run_tile(d.col_cfg, d.nrow_items > 0 ? d.out : d.in, d.out, a.tw + a.tw_off[d.col_cfg],
-                 a.tw_cnt[d.col_cfg], d.rows, d.cols, t0, cnt, flags, s, lds);
+        const float2* src = d.m1 > 1 ? d.work : (d.nrow_items > 0 ? d.out : d.in);
+        run_tile(d.col_cfg, src, d.out, a.tw + a.tw_off[d.col_cfg], a.tw_cnt[d.col_cfg], d.rows, d.cols, d.m1,
+                 t0, cnt, flags, s, lds);
       }
       __syncthreads();  // the LDS of this item is free before the next item starts
     }
@@ -315,7 +378,9 @@ const PassKernel* cfg_table() {
       bdesc<BR4096>(), bdesc<BR8192>(), bdesc<BR16384>(), PassKernel{},  PassKernel{},    bdesc<BC2>(),
       bdesc<BC4>(),   bdesc<BC8>(),    bdesc<BC16>(),   bdesc<BC32>(),  bdesc<BC64>(),   bdesc<BC128>(),
       bdesc<BC256>(), bdesc<BC512>(),  bdesc<BC1024>(), bdesc<BC2048>(), bdesc<BC4096>(), bdesc<BC8192>(),
-      bdesc<BC16384>(), PassKernel{},
+      bdesc<BC16384>(), PassKernel{},  PassKernel{},   PassKernel{},    PassKernel{},    PassKernel{},
+      PassKernel{},   PassKernel{},    PassKernel{},    PassKernel{},   PassKernel{},    bdesc<BRC512>(),
+      bdesc<BRC1024>(), bdesc<BRC2048>(), bdesc<BRC4096>(), bdesc<BRC8192>(), PassKernel{}, PassKernel{},
   };
   return tab;
 }
@@ -326,12 +391,30 @@ int ilog2i(int64_t n) {
   return k;
 }
 
+// Split factor of an M x N transform in a batched plan (1 = plain). Column
+// tiles of 2048 or more points per column hold at most 8 columns (64-byte row
+// segments) and are the batched kernel's slowest items; such a transform is
+// split as in the plain path when a row-with-combine configuration exists for
+// N (512 <= N <= 8192, M1 = its row count) and leaves columns of at most 1024
+// points (tiles of at least 16 columns).
+int batched_split(int M, int N) {
+  if (M < 2048 || N < 512 || N > 8192) return 1;
+  const PassKernel& k = cfg_table()[32 + ilog2i(N)];
+  const int m1 = k.C;
+  if (k.L != N || m1 < 2 || M % m1 != 0 || M / m1 > 1024) return 1;
+  return m1;
+}
+
 }  // namespace
 
 struct BatchedPlan {
   int64_t count = 0;
   std::vector<int32_t> rows, cols;
   std::vector<int32_t> row_cfg, col_cfg, nrow, ncol;
+  std::vector<int32_t> m1;          // split factor per transform (1 = plain)
+  std::vector<int64_t> work_off;    // split transforms: offset in d_work (points)
+  int64_t work_points = 0;
+  int n_split = 0;
   int64_t total_points = 0;
   double flops = 0;
   int num_cu = 0;
@@ -351,6 +434,8 @@ struct BatchedPlan {
   int n_groups = 0;
   int qbeg[kMaxQueues + 1] = {};
   unsigned* d_counters = nullptr;
+  float2* d_work = nullptr;   // intermediate grids of split transforms
+  int twc_off[16] = {};       // offset of W_M^j (j < M) in d_tw, index log2 M (split transforms)
   unsigned* h_err = nullptr;  // pinned, coherent: written by the kernel when a wait gives up
   int max_spins = 0;
   float2* d_tw = nullptr;
@@ -372,15 +457,16 @@ struct Schedule {
 };
 
 // Points one item moves (its data size / 8 bytes): tiles t0 .. t0 + cnt - 1.
+// A split transform's column vectors are its m1 * N columns of M / m1 points.
 int64_t item_points(const BatchedPlan& bp, const PassKernel* tab, int f, int kind, int t0, int cnt) {
-  const int64_t M = bp.rows[(size_t)f], N = bp.cols[(size_t)f];
+  const int64_t M = bp.rows[(size_t)f], N = bp.cols[(size_t)f], m1 = bp.m1[(size_t)f];
   if (kind == kCopyItem) return 1;
   if (kind == kRowItem) {
     const int64_t C = tab[bp.row_cfg[(size_t)f]].C;
     return std::min<int64_t>(C * cnt, M - (int64_t)t0 * C) * N;
   }
   const int64_t C = tab[bp.col_cfg[(size_t)f]].C;
-  return std::min<int64_t>(C * cnt, N - (int64_t)t0 * C) * M;
+  return std::min<int64_t>(C * cnt, m1 * N - (int64_t)t0 * C) * (M / m1);
 }
 
 // Build the queues. Transforms go to the XCD with the least assigned points
@@ -603,16 +689,26 @@ fft2d_status create_batched(int64_t count, const int64_t* rows, const int64_t* c
   };
   bp->count = count;
   const PassKernel* tab = cfg_table();
+  const char* split_env = std::getenv("FFT2D_BATCH_SPLIT");
+  const bool allow_split = !(split_env && std::string(split_env) == "off");
   for (int64_t i = 0; i < count; ++i) {
     const int M = (int)rows[i], N = (int)cols[i];
     bp->rows.push_back(M);
     bp->cols.push_back(N);
-    const int rc = N > 1 ? ilog2i(N) : 0;
-    const int cc = M > 1 ? 16 + ilog2i(M) : 0;
+    const int m1 = allow_split ? batched_split(M, N) : 1;
+    bp->m1.push_back(m1);
+    bp->work_off.push_back(m1 > 1 ? bp->work_points : 0);
+    if (m1 > 1) {
+      bp->work_points += (int64_t)M * N;
+      ++bp->n_split;
+    }
+    // split: M / m1 row tiles of m1 rows (combine), columns of M / m1 points in m1 row blocks
+    const int rc = m1 > 1 ? 32 + ilog2i(N) : (N > 1 ? ilog2i(N) : 0);
+    const int cc = M > 1 ? 16 + ilog2i(M / m1) : 0;
     bp->row_cfg.push_back(rc);
     bp->col_cfg.push_back(cc);
     bp->nrow.push_back(N > 1 ? (M + tab[rc].C - 1) / tab[rc].C : 0);
-    bp->ncol.push_back(M > 1 ? (N + tab[cc].C - 1) / tab[cc].C : 0);
+    bp->ncol.push_back(M > 1 ? (int)(((int64_t)m1 * N + tab[cc].C - 1) / tab[cc].C) : 0);
     bp->total_points += (int64_t)M * N;
     const double p = (double)M * N;
     bp->flops += p > 1 ? 5.0 * p * std::log2(p) : 0.0;
@@ -673,6 +769,19 @@ fft2d_status create_batched(int64_t count, const int64_t* rows, const int64_t* c
       host.resize(host.size() + n);
       if (n) fill_twiddles(tab[c], host.data() + bp->tw_off[c]);
     }
+    // W_M^j = exp(-2 pi i j / M), j < M, for the column length M of every split
+    // transform (the combine's twiddles), each from its own FP64 cos / sin
+    for (int64_t i = 0; i < count; ++i) {
+      if (bp->m1[(size_t)i] == 1) continue;
+      const int lg = ilog2i(bp->rows[(size_t)i]);
+      if (bp->twc_off[lg] != 0) continue;
+      const int64_t M = bp->rows[(size_t)i];
+      bp->twc_off[lg] = (int)host.size();
+      for (int64_t j = 0; j < M; ++j) {
+        const double a = 2.0 * M_PI * (double)j / (double)M;
+        host.push_back(make_float2((float)std::cos(a), (float)(-std::sin(a))));
+      }
+    }
     if (host.empty()) host.push_back(make_float2(0.f, 0.f));
     if ((e = hipMalloc((void**)&bp->d_tw, host.size() * sizeof(float2))) != hipSuccess) return hipfail(e, "twiddles");
     if ((e = hipMemcpy(bp->d_tw, host.data(), host.size() * sizeof(float2), hipMemcpyHostToDevice)) != hipSuccess)
@@ -684,6 +793,9 @@ fft2d_status create_batched(int64_t count, const int64_t* rows, const int64_t* c
     return hipfail(e, "pinned descriptor staging");
   if ((e = hipMalloc((void**)&bp->d_counters, (size_t)(kCounterBase + count) * sizeof(unsigned))) != hipSuccess)
     return hipfail(e, "counters");
+  if (bp->work_points > 0 &&
+      (e = hipMalloc((void**)&bp->d_work, (size_t)bp->work_points * sizeof(float2))) != hipSuccess)
+    return hipfail(e, "work buffer of split transforms");
   if ((e = hipHostMalloc((void**)&bp->h_err, sizeof(unsigned), hipHostMallocCoherent | hipHostMallocMapped)) !=
       hipSuccess)
     return hipfail(e, "pinned error word");
@@ -705,6 +817,9 @@ fft2d_status create_batched(int64_t count, const int64_t* rows, const int64_t* c
     d.row_cfg = bp->row_cfg[(size_t)i];
     d.col_cfg = bp->col_cfg[(size_t)i];
     d.nrow_items = bp->nrow[(size_t)i];
+    d.m1 = bp->m1[(size_t)i];
+    d.work = d.m1 > 1 ? bp->d_work + bp->work_off[(size_t)i] : nullptr;
+    d.twc_off = d.m1 > 1 ? bp->twc_off[ilog2i(d.rows)] : 0;
     d.pad = 0;
   }
 
@@ -713,7 +828,7 @@ fft2d_status create_batched(int64_t count, const int64_t* rows, const int64_t* c
   const char* tune_env = std::getenv("FFT2D_TUNE");
   const std::string mode = tune_env ? tune_env : "cached";
   std::ostringstream keys;
-  keys << "gfx950|v2|" << shape_signature(*bp);
+  keys << "gfx950|v3|" << (bp->n_split ? "split|" : "") << shape_signature(*bp);
   char keyhex[32];
   std::snprintf(keyhex, sizeof(keyhex), "%016llx", (unsigned long long)fnv1a(keys.str()));
   bool have = false;
@@ -859,6 +974,7 @@ void destroy_batched(BatchedPlan* bp) {
   if (bp->d_items) (void)hipFree(bp->d_items);
   if (bp->d_groups) (void)hipFree(bp->d_groups);
   if (bp->d_counters) (void)hipFree(bp->d_counters);
+  if (bp->d_work) (void)hipFree(bp->d_work);
   if (bp->h_err) (void)hipHostFree(bp->h_err);
   if (bp->d_tw) (void)hipFree(bp->d_tw);
   delete bp;
@@ -867,7 +983,8 @@ void destroy_batched(BatchedPlan* bp) {
 std::string describe_batched(const BatchedPlan* bp) {
   std::ostringstream os;
   os << "batched count=" << bp->count << " points=" << bp->total_points << " items=" << bp->n_items
-     << " groups=" << bp->n_groups << " group_kib=" << bp->group_kib << " queues=" << bp->nq
+     << " groups=" << bp->n_groups << " group_kib=" << bp->group_kib << " split=" << bp->n_split
+     << " queues=" << bp->nq
      << (bp->fenced ? " fenced" : " xcd-local") << " grid=" << bp->grid_mult << "x" << bp->num_cu
      << " order=" << (bp->order ? "chunked" : "rows-then-columns") << " tune=" << bp->tune_source
      << " threads=" << kThreads << " lds=" << kLdsElems * 8;

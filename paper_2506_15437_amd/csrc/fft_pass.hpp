@@ -448,23 +448,22 @@ __global__ __launch_bounds__(K::THREADS) __attribute__((amdgpu_waves_per_eu(WPE)
 }
 
 // Row pass with combine (first half of a split column transform, see
-// PassArgs): workgroup w = (grid g, m2) transforms the M1 = C rows
-// M2*m1 + m2, then for every column position an M1-point DFT across those rows
-// and the twiddle W_M^(m2 k1), stored to row M2*k1 + m2. The rows' transformed
-// points are exchanged through LDS in Q rounds of L/Q positions; in each round
-// every thread owns L/(Q*THREADS) positions and all M1 rows of each.
-template <class K, int DIR, int WPE = 1, int SB = 0, bool NT = false>
-__global__ __launch_bounds__(K::THREADS) __attribute__((amdgpu_waves_per_eu(WPE))) void rowc_kernel(PassArgs a) {
+// PassArgs): tile w = (grid g, m2) transforms the M1 = C rows M2*m1 + m2,
+// then for every column position an M1-point DFT across those rows and the
+// twiddle W_M^(m2 k1), stored to row M2*k1 + m2. The rows' transformed points
+// are exchanged through LDS in Q rounds of L/Q positions; in each round every
+// thread owns L/(Q*THREADS) positions and all M1 rows of each. Only
+// io.conj_in is honoured (the output is an intermediate, never final).
+template <class K, int DIR, int AUX = 0, int SB = 0>
+__device__ __forceinline__ void rowc_tile(const PassArgs& a, int64_t w, float2* lds, TileIO io) {
   static_assert(K::valid() && !K::COL && K::C >= 2 && K::P > 1, "invalid combine configuration");
   constexpr int M1 = K::C;
   constexpr int NQ = K::L / K::Q;
   constexpr int NPOS = NQ / K::THREADS;
   static_assert(NPOS >= 1 && NQ % K::THREADS == 0, "positions per thread must be whole");
-  __shared__ float2 lds[K::LDS_ELEMS];
   const int t = threadIdx.x;
   const int c = t / K::T;
   const int tt = t % K::T;
-  const int64_t w = blockIdx.x;
   const int64_t g = w / a.m2;
   const int64_t m2 = w - g * a.m2;
   const int64_t gbase = g * a.m2 * M1 * K::L;
@@ -478,8 +477,9 @@ __global__ __launch_bounds__(K::THREADS) __attribute__((amdgpu_waves_per_eu(WPE)
   float2 d[K::E];
   static_for<0, K::E>([&](auto J) {
     constexpr int j = decltype(J)::value;
-    d[j] = src.load<NT ? kAuxNontemporal : 0>(voff_in, (uint32_t)(K::T * j) * 8u);
+    d[j] = src.load<AUX>(voff_in, (uint32_t)(K::T * j) * 8u);
   });
+  if (io.conj_in) static_for<0, K::E>([&](auto J) { d[decltype(J)::value].y = -d[decltype(J)::value].y; });
   static_for<0, K::P>([&](auto Pp) { run_pass<K, DIR, decltype(Pp)::value, SB>(d, lds, tt, c, tw); });
   float2 wk[M1];
   static_for<1, M1>([&](auto Kk) {
@@ -514,6 +514,12 @@ __global__ __launch_bounds__(K::THREADS) __attribute__((amdgpu_waves_per_eu(WPE)
     });
     __syncthreads();
   });
+}
+
+template <class K, int DIR, int WPE = 1, int SB = 0, bool NT = false>
+__global__ __launch_bounds__(K::THREADS) __attribute__((amdgpu_waves_per_eu(WPE))) void rowc_kernel(PassArgs a) {
+  __shared__ float2 lds[K::LDS_ELEMS];
+  rowc_tile<K, DIR, NT ? kAuxNontemporal : 0, SB>(a, blockIdx.x, lds, TileIO{});
 }
 
 template <class K, int WPE, bool NT>

@@ -63,6 +63,45 @@ def test_batched_mixed_shapes(F, tune, sync, monkeypatch):
         plan.close()
 
 
+# tall transforms: split (row pass with combine + short columns) where a
+# combine configuration exists for the row length, plain otherwise
+SPLIT_SHAPES = [(2048, 512), (2048, 1024), (2048, 2048), (2048, 4096), (2048, 8192), (4096, 1024), (8192, 2048),
+                (16384, 512), (4096, 8192), (2048, 256), (32, 32)]
+SPLIT_EXPECTED = 8  # the first eight are split
+
+
+@pytest.mark.parametrize("split", ["auto", "off"])
+def test_batched_split_transforms(F, split, monkeypatch):
+    """Forward, inverse and in place for tall grids in one plan, split (row pass
+    with an M1-point combine into a plan work buffer, columns of M / M1) or not."""
+    import torch
+    monkeypatch.setenv("FFT2D_TUNE", "off")
+    monkeypatch.setenv("FFT2D_BATCH_SPLIT", split)
+    say("case batched split=%s" % split)
+    xs = synth.batched_grids(14, SPLIT_SHAPES)
+    plan = F.BatchedPlan(SPLIT_SHAPES)
+    try:
+        desc = plan.describe()
+        say(desc)
+        assert (" split=%d " % (SPLIT_EXPECTED if split == "auto" else 0)) in desc, desc
+        ins, ys = _run(F, plan, xs, F.FORWARD)
+        _, zs = _run(F, plan, xs, F.INVERSE)
+        worst_f = worst_i = 0.0
+        for x, y, z, s in zip(xs, ys, zs, SPLIT_SHAPES):
+            ef = rel_l2(host(y), oracle.fft2_forward(x))
+            ei = rel_l2(host(z), oracle.ifft2(x))
+            worst_f, worst_i = max(worst_f, ef), max(worst_i, ei)
+            assert ef <= TOL and ei <= TOL, (s, ef, ei)
+        say("batched split=%s worst rel_l2 fwd=%.3e inv=%.3e" % (split, worst_f, worst_i))
+        inplace = [t.clone() for t in ins]
+        plan(inplace, F.FORWARD, inplace)
+        torch.cuda.synchronize()
+        for u, v in zip(ys, inplace):
+            assert torch.equal(u, v)
+    finally:
+        plan.close()
+
+
 def test_batched_replay_pointer_change_and_in_place(F, monkeypatch):
     import torch
     monkeypatch.setenv("FFT2D_TUNE", "off")
