@@ -183,6 +183,26 @@ const char* fft2d_last_error(void);
  */
 fft2d_status fft2d_plan_describe(fft2d_plan_t plan, char* buf, int64_t buflen);
 
+/*
+ * fft2d_plan_twiddles -- copy one of a uniform plan's FP32 twiddle tables to
+ * host memory, for inspection and tests (synchronous: it waits for the copy).
+ *   which    : 0 = the row pass's table, 1 = the column pass's table, 2 = the
+ *              combine table of a split plan, W_rows^j = exp(-2 pi i j / rows)
+ *              for j < rows.
+ *   host_out : complex64 host buffer of `capacity` entries (may be NULL when
+ *              capacity is 0); min(capacity, *count) entries are written.
+ *   count    : receives the table's size (0 if the plan has no such table).
+ * Pass tables cover passes p >= 1 of the pass's radix schedule (reported by
+ * fft2d_plan_describe): with R = radix p and Ns the product of the earlier
+ * radices, entry (r, k), r in [1, R), k in [0, Ns), is exp(-2 pi i k r / (Ns R)),
+ * stored pass after pass, r-major within a pass. Every entry is computed in
+ * FP64 from its own angle and rounded once to FP32 (the paper's Section 4
+ * precomputes its twiddles once at start-up).
+ * Errors: FFT2D_ERR_WRONG_PLAN_KIND for a batched plan,
+ * FFT2D_ERR_INVALID_SIZE for another `which`.
+ */
+fft2d_status fft2d_plan_twiddles(fft2d_plan_t plan, int which, void* host_out, int64_t capacity, int64_t* count);
+
 /* Library version as MAJOR*10000 + MINOR*100 + PATCH. */
 int fft2d_version(void);
 

@@ -40,7 +40,8 @@ STATUS_NAMES = {
 
 # Every symbol the public header declares.
 EXPORTS = ("fft2d_plan", "fft2d_plan_batched", "fft2d_exec", "fft2d_exec_pass", "fft2d_exec_batched",
-           "fft2d_backward", "fft2d_destroy", "fft2d_status_string", "fft2d_last_error", "fft2d_plan_describe", "fft2d_version")
+           "fft2d_backward", "fft2d_destroy", "fft2d_status_string", "fft2d_last_error", "fft2d_plan_describe",
+           "fft2d_plan_twiddles", "fft2d_version")
 
 
 class Fft2dError(RuntimeError):
@@ -71,10 +72,11 @@ def _load():
     lib.fft2d_last_error.argtypes = []
     lib.fft2d_last_error.restype = ctypes.c_char_p
     lib.fft2d_plan_describe.argtypes = [vp, ctypes.c_char_p, i64]
+    lib.fft2d_plan_twiddles.argtypes = [vp, ci, vp, i64, ctypes.POINTER(i64)]
     lib.fft2d_version.argtypes = []
     lib.fft2d_version.restype = ci
     for f in ("fft2d_plan", "fft2d_plan_batched", "fft2d_exec", "fft2d_exec_pass", "fft2d_exec_batched", "fft2d_backward",
-              "fft2d_destroy", "fft2d_plan_describe"):
+              "fft2d_destroy", "fft2d_plan_describe", "fft2d_plan_twiddles"):
         getattr(lib, f).restype = ci
     return lib
 
@@ -149,6 +151,17 @@ def fft2d_backward(plan: int, grad_out_ptr: int, grad_in_ptr: int, forward_direc
 
 def fft2d_destroy(plan: int) -> None:
     _check(lib.fft2d_destroy(plan), "fft2d_destroy")
+
+
+def fft2d_plan_twiddles(plan: int, which: int) -> np.ndarray:
+    """One of a uniform plan's FP32 twiddle tables as complex64 (0 row pass, 1 column pass, 2 combine)."""
+    n = ctypes.c_int64(0)
+    _check(lib.fft2d_plan_twiddles(plan, int(which), None, 0, ctypes.byref(n)), "fft2d_plan_twiddles")
+    out = np.zeros(max(n.value, 0), dtype=np.complex64)
+    if n.value > 0:
+        _check(lib.fft2d_plan_twiddles(plan, int(which), out.ctypes.data, n.value, ctypes.byref(n)),
+               "fft2d_plan_twiddles")
+    return out
 
 
 def fft2d_plan_describe(plan: int) -> str:

@@ -10,6 +10,7 @@
 #include "fft_batched.h"
 #include "fft_internal.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -459,6 +460,33 @@ fft2d_status fft2d_plan_describe(fft2d_plan_t plan, char* buf, int64_t buflen) {
     d = describe_batched(plan->batched);
   }
   std::snprintf(buf, (size_t)buflen, "%s", d.c_str());
+  return FFT2D_OK;
+}
+
+fft2d_status fft2d_plan_twiddles(fft2d_plan_t plan, int which, void* host_out, int64_t capacity, int64_t* count) {
+  if (!plan || !count) return fail(FFT2D_ERR_NULL_POINTER, "plan or count pointer is NULL");
+  if (!is_live(plan)) return fail(FFT2D_ERR_INVALID_PLAN, "plan handle is not live");
+  if (plan->kind != kUniform) return fail(FFT2D_ERR_WRONG_PLAN_KIND, "twiddle tables belong to uniform plans");
+  if (which < 0 || which > 2) return fail(FFT2D_ERR_INVALID_SIZE, "which must be 0 (row), 1 (column) or 2 (combine)");
+  const float2* dev = nullptr;
+  int64_t n = 0;
+  if (which == 0 && plan->row_k) {
+    dev = plan->tw_row;
+    n = (int64_t)twiddle_count(*plan->row_k);
+  } else if (which == 1 && plan->col_k) {
+    dev = plan->tw_col;
+    n = (int64_t)twiddle_count(*plan->col_k);
+  } else if (which == 2 && plan->m1 > 1) {
+    dev = plan->tw_comb;
+    n = plan->rows;
+  }
+  *count = n;
+  const int64_t copy = std::min<int64_t>(n, capacity);
+  if (copy > 0) {
+    if (!host_out) return fail(FFT2D_ERR_NULL_POINTER, "output buffer is NULL");
+    const hipError_t e = hipMemcpy(host_out, dev, (size_t)copy * sizeof(float2), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "twiddle download");
+  }
   return FFT2D_OK;
 }
 

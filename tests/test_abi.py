@@ -41,7 +41,7 @@ def test_library_exports_every_declared_symbol(L):
 
 def test_status_strings_and_version(L):
     assert L.status_string(0) == "success"
-    for code in range(1, 10):
+    for code in range(1, 11):
         s = L.status_string(code)
         assert s and s != "unknown status"
     assert L.status_string(99) == "unknown status"
@@ -83,6 +83,10 @@ def test_exec_rejects_null_and_dead_plans(L):
     assert L.lib.fft2d_destroy(None) == 0
     buf = ctypes.create_string_buffer(16)
     assert L.lib.fft2d_plan_describe(bogus, buf, 16) == 8
+    n = ctypes.c_int64(-1)
+    assert L.lib.fft2d_plan_twiddles(None, 0, None, 0, ctypes.byref(n)) == 1
+    assert L.lib.fft2d_plan_twiddles(bogus, 0, None, 0, None) == 1
+    assert L.lib.fft2d_plan_twiddles(bogus, 0, None, 0, ctypes.byref(n)) == 8
 
 
 def test_last_error_is_thread_local(L):
