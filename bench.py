@@ -410,6 +410,32 @@ def cpu_baseline(rows, cols, x, budget_s, max_reps, threads=0):
                            "over rows then columns, %.1f s" % (reps, rows, cols, dt)}
 
 
+def cpu_configs(threads=0):
+    """The FP64 oracle's forward transform of each configuration once (all host
+    cores), for GPU/CPU context beside the 4096^2 baseline."""
+    import oracle
+    import synth
+    cases = [("1024x1024 forward", (1024, 1024), 0), ("8192x8192 forward", (8192, 8192), 2),
+             ("16384x2048 forward", (16384, 2048), 3), ("8 x 2048x2048 forward", (8, 2048, 2048), 5)]
+    out = {}
+    for name, shape, seed in cases:
+        x = synth.complex_grid(seed, shape)
+        t0 = time.perf_counter()
+        oracle.fft2_forward(x, threads)
+        dt = time.perf_counter() - t0
+        batch = shape[0] if len(shape) == 3 else 1
+        out[name] = {"seconds": round(dt, 4), "gflops": round(flops_2d(shape[-2], shape[-1], batch) / dt / 1e9, 2)}
+    shapes = synth.pow2_shapes(4, 512)
+    xs = synth.batched_grids(4, shapes)
+    t0 = time.perf_counter()
+    for x in xs:
+        oracle.fft2_forward(x, threads)
+    dt = time.perf_counter() - t0
+    out["512 shapes 2^a x 2^b forward"] = {"seconds": round(dt, 4),
+                                           "gflops": round(sum(flops_2d(r, c) for r, c in shapes) / dt / 1e9, 2)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -513,6 +539,9 @@ def main():
         log("bench: CPU baseline on one core")
         _, cpu1 = cpu_baseline(rows, cols, r["x"], 4.0, 50, threads=1)
         result["cpu_baseline_1core"] = cpu1
+        if not args.no_extras:
+            log("bench: FP64 oracle on the other configurations (context)")
+            result["cpu_oracle_configs"] = cpu_configs()
         num = np.linalg.norm((r["y"].astype(np.complex128) - ref).ravel())
         result["fwd_rel_l2_vs_oracle"] = float(num / np.linalg.norm(ref.ravel()))
 

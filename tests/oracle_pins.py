@@ -19,6 +19,7 @@ Pins:
                         Hermitian symmetry of real input, rows/columns order,
                         inverse round trip
   library             : numpy.fft (pocketfft), run as a black box
+  matrix              : the separable matrix form F_M x F_N^T of the definition
   adjoint             : Re<F a, b> == Re<a, F^H b>, both directions
 """
 
@@ -231,6 +232,26 @@ def pin_library(o, shapes=((32, 64), (256, 128), (1024, 1024), (16384, 8), (4, 1
     return fails
 
 
+def _dft_matrix(n, sign):
+    """F[k, m] = exp(sign 2 pi i (k m mod n) / n), the phase reduced in integers."""
+    k = np.arange(n, dtype=np.int64)
+    return np.exp(sign * 2j * np.pi * (np.outer(k, k) % n) / n)
+
+
+def pin_matrix(o, shapes=((4, 8), (64, 32), (128, 256), (256, 256))):
+    """The separable matrix form of the definition: X = F_M x F_N^T."""
+    fails = []
+    rng = np.random.default_rng(17)
+    for (M, N) in shapes:
+        x = _rand(rng, (M, N))
+        for sign, scale in ((-1, 1.0), (1, 1.0 / (M * N))):
+            ref = scale * (_dft_matrix(M, sign) @ x @ _dft_matrix(N, sign).T)
+            err = _rel(o.fft2(x, sign, scale), ref)
+            if not err <= 1e-12:
+                fails.append("matrix %dx%d sign=%d err=%.3g" % (M, N, sign, err))
+    return fails
+
+
 def pin_adjoint(o, shapes=((16, 32), (64, 64))):
     fails = []
     rng = np.random.default_rng(16)
@@ -247,7 +268,7 @@ def pin_adjoint(o, shapes=((16, 32), (64, 64))):
 
 
 ALL_PINS = (pin_direct1d, pin_direct2d, pin_listing, pin_schedule, pin_ramp8, pin_closed_forms, pin_invariants,
-            pin_library, pin_adjoint)
+            pin_library, pin_matrix, pin_adjoint)
 
 
 def run_all(o, quick=False):
