@@ -221,18 +221,29 @@ int oracle_dft2d_direct(const double* in, double* out, int64_t M, int64_t N, int
   return 0;
 }
 
+#ifdef _OPENMP
+/* The process's OpenMP thread count before any call of this file changed it. */
+static int default_threads(void) {
+  static int n = 0;
+  if (n == 0) n = omp_get_max_threads();
+  return n;
+}
+#endif
+
 /*
  * 2D transform of `batch` grids of M x N. complex64 input `in` (may be NULL if
  * `in64` is given instead), complex128 output `out`. Every row gets a length-N
  * transform, then every column a length-M transform; the result is multiplied
  * by `scale` (1 for the forward transform, 1/(M N) for the inverse).
- * `threads` <= 0 keeps the OpenMP default.
+ * `threads` <= 0 uses the OpenMP default of the process (every call sets the
+ * count, so an earlier call with a small count does not stick).
  */
 int oracle_fft2d(const float* in, const double* in64, double* out, int64_t batch, int64_t M, int64_t N,
                  int sign, double scale, int threads) {
   if ((!in && !in64) || !out || batch < 0 || !is_pow2(M) || !is_pow2(N) || (sign != 1 && sign != -1)) return -1;
 #ifdef _OPENMP
-  if (threads > 0) omp_set_num_threads(threads);
+  const int all = default_threads();  /* captured before the first change */
+  omp_set_num_threads(threads > 0 ? threads : all);
 #else
   (void)threads;
 #endif
@@ -294,10 +305,10 @@ int oracle_fft2d(const float* in, const double* in64, double* out, int64_t batch
   return status;
 }
 
-/* Number of OpenMP threads a parallel region will use (1 without OpenMP). */
+/* Number of OpenMP threads a parallel region uses by default (1 without OpenMP). */
 int oracle_max_threads(void) {
 #ifdef _OPENMP
-  return omp_get_max_threads();
+  return default_threads();
 #else
   return 1;
 #endif
