@@ -116,7 +116,7 @@ struct BatchDesc {
   int32_t pad;
 };
 
-enum ItemKind { kRowItem = 0, kColItem = 1, kCopyItem = 2 };
+enum ItemKind { kRowItem = 0, kColItem = 1, kCopyItem = 2, kGridItem = 3 };
 
 constexpr int kMaxQueues = 8;
 constexpr int kQueueStride = 32;                     // queue heads 128 bytes apart
@@ -239,6 +239,84 @@ __device__ __forceinline__ void run_ctile(int cfg, const float2* in, float2* wor
   }
 }
 
+// Whole-grid item: a small M x N grid in one workgroup and one pass through
+// HBM. The NRT row tiles of configuration KR are loaded from global memory and
+// transformed in registers one after the other, the grid goes through LDS in
+// row-major order, and the NCT column tiles of KC are read from there,
+// transformed and stored. The LDS holding the grid is the exchange area of the
+// passes: it is written only after the last row pass and released (barrier)
+// before the first column pass.
+template <class KR, class KC, int M, int N>
+__device__ __noinline__ __attribute__((flatten)) void grid_item(const float2* in, float2* out, const float2* twr,
+                                                                int twr_count, const float2* twc, int twc_count,
+                                                                int flags, float scale, float2* lds) {
+  static_assert(!KR::COL && KC::COL && KR::L == N && KC::L == M, "row and column configurations of the grid");
+  static_assert(KR::THREADS == kThreads && KC::THREADS == kThreads, "batched configurations use 512 threads");
+  static_assert(M % KR::C == 0 && N % KC::C == 0 && M * N <= kLdsElems, "whole tiles, grid fits the LDS");
+  constexpr int NRT = M / KR::C;
+  constexpr int NCT = N / KC::C;
+  const Buf src(uniform(in), (uint32_t)(M * N) * 8u);
+  const Buf dst(uniform(out), (uint32_t)(M * N) * 8u);
+  const Buf tr(uniform(twr), (uint32_t)uniform(twr_count) * 8u);
+  const Buf tc(uniform(twc), (uint32_t)uniform(twc_count) * 8u);
+  flags = uniform(flags);
+  scale = uniform(scale);
+  const int t = threadIdx.x;
+  const int cr = t / KR::T, ttr = t % KR::T;  // row tiles: row cr of the tile, points ttr + T j
+  const int cc = t % KC::C, ttc = t / KC::C;  // column tiles: column cc of the tile, points ttc + T j
+  float2 dr[NRT][KR::E];
+  static_for<0, NRT>([&](auto U) {
+    constexpr int u = decltype(U)::value;
+    const uint32_t voff = (uint32_t)((u * KR::C + cr) * N + ttr) * 8u;
+    static_for<0, KR::E>([&](auto J) {
+      constexpr int j = decltype(J)::value;
+      dr[u][j] = src.load(voff, (uint32_t)(KR::T * j) * 8u);
+      if (flags & 1) dr[u][j].y = -dr[u][j].y;
+    });
+    static_for<0, KR::P>([&](auto Pp) { run_pass<KR, -1, decltype(Pp)::value>(dr[u], lds, ttr, cr, tr); });
+  });
+  __syncthreads();
+  static_for<0, NRT>([&](auto U) {
+    constexpr int u = decltype(U)::value;
+    static_for<0, KR::E>([&](auto J) {
+      constexpr int j = decltype(J)::value;
+      lds[(u * KR::C + cr) * N + ttr + KR::T * j] = dr[u][j];
+    });
+  });
+  __syncthreads();
+  float2 dcl[NCT][KC::E];
+  static_for<0, NCT>([&](auto U) {
+    constexpr int u = decltype(U)::value;
+    static_for<0, KC::E>([&](auto J) {
+      constexpr int j = decltype(J)::value;
+      dcl[u][j] = lds[(ttc + KC::T * j) * N + u * KC::C + cc];
+    });
+  });
+  __syncthreads();
+  const float sy = (flags & 2) ? -scale : scale;
+  static_for<0, NCT>([&](auto U) {
+    constexpr int u = decltype(U)::value;
+    static_for<0, KC::P>([&](auto Pp) { run_pass<KC, -1, decltype(Pp)::value>(dcl[u], lds, ttc, cc, tc); });
+    const uint32_t voff = (uint32_t)(ttc * N + u * KC::C + cc) * 8u;
+    static_for<0, KC::E>([&](auto J) {
+      constexpr int j = decltype(J)::value;
+      dst.store(make_float2(dcl[u][j].x * scale, dcl[u][j].y * sy), voff, (uint32_t)(KC::T * j * N) * 8u);
+    });
+  });
+}
+
+// The grids handled as whole-grid items (see batched_grid_item on the host).
+__device__ __forceinline__ void run_grid(int rows, int cols, const float2* in, float2* out, const float2* twr,
+                                         int twr_count, const float2* twc, int twc_count, int flags, float scale,
+                                         float2* lds) {
+  if (rows == 64 && cols == 64)
+    grid_item<BR64, BC64, 64, 64>(in, out, twr, twr_count, twc, twc_count, flags, scale, lds);
+  else if (rows == 64 && cols == 128)
+    grid_item<BR128, BC64, 64, 128>(in, out, twr, twr_count, twc, twc_count, flags, scale, lds);
+  else if (rows == 128 && cols == 64)
+    grid_item<BR64, BC128, 128, 64>(in, out, twr, twr_count, twc, twc_count, flags, scale, lds);
+}
+
 #define FFT2D_TILE_ARGS in, out, tw, tw_count, rows, cols, m1, t0, cnt, flags, scale, lds
 __device__ __forceinline__ void run_tile(int cfg, const float2* in, float2* out, const float2* tw, int tw_count,
                                          int rows, int cols, int m1, int t0, int cnt, int flags, float scale,
@@ -315,6 +393,13 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
           const float2 v = d.in[0];
           d.out[0] = make_float2(v.x * s, v.y * s);
         }
+        continue;
+      }
+      if (kind == kGridItem) {
+        // the inverse conjugates on load, then conjugates and scales on store
+        run_grid(d.rows, d.cols, d.in, d.out, a.tw + a.tw_off[d.row_cfg], a.tw_cnt[d.row_cfg],
+                 a.tw + a.tw_off[d.col_cfg], a.tw_cnt[d.col_cfg], inv ? 3 : 0, s, lds);
+        __syncthreads();  // the LDS of this item is free before the next item starts
         continue;
       }
       if (kind == kRowItem) {
@@ -397,6 +482,13 @@ int ilog2i(int64_t n) {
 // split as in the plain path when a row-with-combine configuration exists for
 // N (512 <= N <= 8192, M1 = its row count) and leaves columns of at most 1024
 // points (tiles of at least 16 columns).
+// Grids done as one whole-grid item (one workgroup, one pass through HBM):
+// the shapes whose row and column configurations cover the grid in whole
+// tiles with at most 16 points per thread (see grid_item).
+bool batched_grid_item(int M, int N) {
+  return (M == 64 && N == 64) || (M == 64 && N == 128) || (M == 128 && N == 64);
+}
+
 int batched_split(int M, int N) {
   if (M < 2048 || N < 512 || N > 8192) return 1;
   const PassKernel& k = cfg_table()[32 + ilog2i(N)];
@@ -412,6 +504,8 @@ struct BatchedPlan {
   std::vector<int32_t> rows, cols;
   std::vector<int32_t> row_cfg, col_cfg, nrow, ncol;
   std::vector<int32_t> m1;          // split factor per transform (1 = plain)
+  std::vector<uint8_t> grid;        // 1: one whole-grid item
+  int n_grid = 0;
   std::vector<int64_t> work_off;    // split transforms: offset in d_work (points)
   int64_t work_points = 0;
   int n_split = 0;
@@ -461,6 +555,7 @@ struct Schedule {
 int64_t item_points(const BatchedPlan& bp, const PassKernel* tab, int f, int kind, int t0, int cnt) {
   const int64_t M = bp.rows[(size_t)f], N = bp.cols[(size_t)f], m1 = bp.m1[(size_t)f];
   if (kind == kCopyItem) return 1;
+  if (kind == kGridItem) return M * N;
   if (kind == kRowItem) {
     const int64_t C = tab[bp.row_cfg[(size_t)f]].C;
     return std::min<int64_t>(C * cnt, M - (int64_t)t0 * C) * N;
@@ -502,6 +597,10 @@ Schedule build_schedule(const BatchedPlan& bp, int order, int group_kib) {
   auto rows_of = [&](int f, std::vector<uint2>& out) {
     if (bp.rows[(size_t)f] == 1 && bp.cols[(size_t)f] == 1) {
       out.push_back(make_uint2((unsigned)f << 2 | kCopyItem, 1u << 16));
+      return;
+    }
+    if (bp.grid[(size_t)f]) {
+      out.push_back(make_uint2((unsigned)f << 2 | kGridItem, 1u << 16));
       return;
     }
     runs(f, kRowItem, bp.nrow[(size_t)f], out);
@@ -691,6 +790,8 @@ fft2d_status create_batched(int64_t count, const int64_t* rows, const int64_t* c
   const PassKernel* tab = cfg_table();
   const char* split_env = std::getenv("FFT2D_BATCH_SPLIT");
   const bool allow_split = !(split_env && std::string(split_env) == "off");
+  const char* grid_env = std::getenv("FFT2D_BATCH_GRID");
+  const bool allow_grid = !(grid_env && std::string(grid_env) == "off");
   for (int64_t i = 0; i < count; ++i) {
     const int M = (int)rows[i], N = (int)cols[i];
     bp->rows.push_back(M);
@@ -705,10 +806,14 @@ fft2d_status create_batched(int64_t count, const int64_t* rows, const int64_t* c
     // split: M / m1 row tiles of m1 rows (combine), columns of M / m1 points in m1 row blocks
     const int rc = m1 > 1 ? 32 + ilog2i(N) : (N > 1 ? ilog2i(N) : 0);
     const int cc = M > 1 ? 16 + ilog2i(M / m1) : 0;
+    const bool whole = allow_grid && m1 == 1 && batched_grid_item(M, N);
+    bp->grid.push_back(whole ? 1 : 0);
+    bp->n_grid += whole ? 1 : 0;
     bp->row_cfg.push_back(rc);
     bp->col_cfg.push_back(cc);
-    bp->nrow.push_back(N > 1 ? (M + tab[rc].C - 1) / tab[rc].C : 0);
-    bp->ncol.push_back(M > 1 ? (int)(((int64_t)m1 * N + tab[cc].C - 1) / tab[cc].C) : 0);
+    // a whole-grid item has no row or column tiles (and nothing to wait for)
+    bp->nrow.push_back(!whole && N > 1 ? (M + tab[rc].C - 1) / tab[rc].C : 0);
+    bp->ncol.push_back(!whole && M > 1 ? (int)(((int64_t)m1 * N + tab[cc].C - 1) / tab[cc].C) : 0);
     bp->total_points += (int64_t)M * N;
     const double p = (double)M * N;
     bp->flops += p > 1 ? 5.0 * p * std::log2(p) : 0.0;
@@ -828,7 +933,7 @@ fft2d_status create_batched(int64_t count, const int64_t* rows, const int64_t* c
   const char* tune_env = std::getenv("FFT2D_TUNE");
   const std::string mode = tune_env ? tune_env : "cached";
   std::ostringstream keys;
-  keys << "gfx950|v3|" << (bp->n_split ? "split|" : "") << shape_signature(*bp);
+  keys << "gfx950|v4|" << (bp->n_split ? "split|" : "") << (bp->n_grid ? "whole|" : "") << shape_signature(*bp);
   char keyhex[32];
   std::snprintf(keyhex, sizeof(keyhex), "%016llx", (unsigned long long)fnv1a(keys.str()));
   bool have = false;
@@ -984,6 +1089,7 @@ std::string describe_batched(const BatchedPlan* bp) {
   std::ostringstream os;
   os << "batched count=" << bp->count << " points=" << bp->total_points << " items=" << bp->n_items
      << " groups=" << bp->n_groups << " group_kib=" << bp->group_kib << " split=" << bp->n_split
+     << " whole=" << bp->n_grid
      << " queues=" << bp->nq
      << (bp->fenced ? " fenced" : " xcd-local") << " grid=" << bp->grid_mult << "x" << bp->num_cu
      << " order=" << (bp->order ? "chunked" : "rows-then-columns") << " tune=" << bp->tune_source

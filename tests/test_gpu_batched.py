@@ -102,6 +102,36 @@ def test_batched_split_transforms(F, split, monkeypatch):
         plan.close()
 
 
+@pytest.mark.parametrize("whole", ["auto", "off"])
+def test_batched_whole_grid_items(F, whole, monkeypatch):
+    """64 x 64, 64 x 128 and 128 x 64 grids run as one item each (one pass through
+    HBM) unless FFT2D_BATCH_GRID=off; forward, inverse and in place match the oracle."""
+    import torch
+    monkeypatch.setenv("FFT2D_TUNE", "off")
+    monkeypatch.setenv("FFT2D_BATCH_GRID", whole)
+    shapes = [(64, 64), (64, 128), (128, 64), (64, 64), (128, 128), (32, 64)] * 3
+    say("case batched whole-grid items %s" % whole)
+    xs = synth.batched_grids(15, shapes)
+    plan = F.BatchedPlan(shapes)
+    try:
+        desc = plan.describe()
+        say(desc)
+        assert (" whole=%d " % (12 if whole == "auto" else 0)) in desc, desc
+        ins, ys = _run(F, plan, xs, F.FORWARD)
+        _, zs = _run(F, plan, xs, F.INVERSE)
+        for x, y, z, s in zip(xs, ys, zs, shapes):
+            ef = rel_l2(host(y), oracle.fft2_forward(x))
+            ei = rel_l2(host(z), oracle.ifft2(x))
+            assert ef <= TOL and ei <= TOL, (s, ef, ei)
+        inplace = [t.clone() for t in ins]
+        plan(inplace, F.FORWARD, inplace)
+        torch.cuda.synchronize()
+        for u, v in zip(ys, inplace):
+            assert torch.equal(u, v)
+    finally:
+        plan.close()
+
+
 def test_batched_replay_pointer_change_and_in_place(F, monkeypatch):
     import torch
     monkeypatch.setenv("FFT2D_TUNE", "off")
