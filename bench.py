@@ -42,16 +42,16 @@ def log(*a):
 
 
 def kernel_source_hash():
-    """SHA-256 over the sources of the plain path (kernels, plan logic, public
-    header): counters taken from an older build do not describe the current one."""
+    """SHA-256 over the sources of the plain path's kernels and plan logic
+    (csrc/, batched sources excluded): counters taken from an older build do not
+    describe the current one."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2506_15437_amd", "csrc")
     files = sorted(f for f in os.listdir(csrc)
                    if f.endswith((".hip", ".hpp", ".h", ".cpp")) and not f.startswith("fft_batched"))
-    for f in files + ["fft2d.h"]:
-        path = os.path.join(csrc, f) if f != "fft2d.h" else os.path.join(ROOT, "include", "fft2d.h")
-        with open(path, "rb") as fh:
+    for f in files:
+        with open(os.path.join(csrc, f), "rb") as fh:
             h.update(f.encode() + b"\0" + fh.read())
     return h.hexdigest()[:16]
 
