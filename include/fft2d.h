@@ -107,8 +107,9 @@ fft2d_status fft2d_plan(fft2d_plan_t* out, int64_t batch, int64_t rows, int64_t 
  * 8192) are split as in fft2d_plan: their row pass combines M1 rows into a
  * plan-owned work buffer of rows*cols complex64 each, and their column pass
  * runs columns of rows/M1 points (FFT2D_BATCH_SPLIT=off disables this).
- * 64x64, 64x128 and 128x64 grids are transformed whole by one workgroup, with
- * one read and one write of their data (FFT2D_BATCH_GRID=off disables this).
+ * Grids of 64x64, 64x128, 128x64, 128x128, 64x256 and 256x64 are transformed
+ * whole by one workgroup, with one read and one write of their data
+ * (FFT2D_BATCH_GRID=off disables this).
  */
 fft2d_status fft2d_plan_batched(fft2d_plan_t* out, int64_t count, const int64_t* rows, const int64_t* cols);
 

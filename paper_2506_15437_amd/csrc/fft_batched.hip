@@ -240,21 +240,23 @@ __device__ __forceinline__ void run_ctile(int cfg, const float2* in, float2* wor
 }
 
 // Whole-grid item: a small M x N grid in one workgroup and one pass through
-// HBM. The NRT row tiles of configuration KR are loaded from global memory and
-// transformed in registers one after the other, the grid goes through LDS in
-// row-major order, and the NCT column tiles of KC are read from there,
-// transformed and stored. The LDS holding the grid is the exchange area of the
-// passes: it is written only after the last row pass and released (barrier)
-// before the first column pass.
+// HBM. Row tile u (configuration KR, C_r rows) is loaded from global memory
+// and transformed in registers; then it crosses LDS in row-major order and
+// every column-tile thread (configuration KC) takes the points of its columns
+// that lie in those rows, so the grid moves through LDS one row tile at a
+// time; finally the column tiles are transformed and stored. The LDS holding a
+// row tile is the passes' exchange area, used between barriers only.
 template <class KR, class KC, int M, int N>
 __device__ __noinline__ __attribute__((flatten)) void grid_item(const float2* in, float2* out, const float2* twr,
                                                                 int twr_count, const float2* twc, int twc_count,
                                                                 int flags, float scale, float2* lds) {
   static_assert(!KR::COL && KC::COL && KR::L == N && KC::L == M, "row and column configurations of the grid");
   static_assert(KR::THREADS == kThreads && KC::THREADS == kThreads, "batched configurations use 512 threads");
-  static_assert(M % KR::C == 0 && N % KC::C == 0 && M * N <= kLdsElems, "whole tiles, grid fits the LDS");
+  static_assert(M % KR::C == 0 && N % KC::C == 0, "whole tiles");
+  static_assert(KR::C % KC::T == 0 && KR::C * N <= kLdsElems, "a row tile holds whole point blocks, fits the LDS");
   constexpr int NRT = M / KR::C;
   constexpr int NCT = N / KC::C;
+  constexpr int JR = KR::C / KC::T;  // column points j of row tile u: u * JR <= j < (u + 1) * JR
   const Buf src(uniform(in), (uint32_t)(M * N) * 8u);
   const Buf dst(uniform(out), (uint32_t)(M * N) * 8u);
   const Buf tr(uniform(twr), (uint32_t)uniform(twr_count) * 8u);
@@ -264,43 +266,41 @@ __device__ __noinline__ __attribute__((flatten)) void grid_item(const float2* in
   const int t = threadIdx.x;
   const int cr = t / KR::T, ttr = t % KR::T;  // row tiles: row cr of the tile, points ttr + T j
   const int cc = t % KC::C, ttc = t / KC::C;  // column tiles: column cc of the tile, points ttc + T j
-  float2 dr[NRT][KR::E];
+  float2 dcl[NCT][KC::E];
   static_for<0, NRT>([&](auto U) {
     constexpr int u = decltype(U)::value;
+    float2 dr[KR::E];
     const uint32_t voff = (uint32_t)((u * KR::C + cr) * N + ttr) * 8u;
     static_for<0, KR::E>([&](auto J) {
       constexpr int j = decltype(J)::value;
-      dr[u][j] = src.load(voff, (uint32_t)(KR::T * j) * 8u);
-      if (flags & 1) dr[u][j].y = -dr[u][j].y;
+      dr[j] = src.load(voff, (uint32_t)(KR::T * j) * 8u);
+      if (flags & 1) dr[j].y = -dr[j].y;
     });
-    static_for<0, KR::P>([&](auto Pp) { run_pass<KR, -1, decltype(Pp)::value>(dr[u], lds, ttr, cr, tr); });
-  });
-  __syncthreads();
-  static_for<0, NRT>([&](auto U) {
-    constexpr int u = decltype(U)::value;
+    if constexpr (u > 0) __syncthreads();  // the previous row tile's points have been read from LDS
+    static_for<0, KR::P>([&](auto Pp) { run_pass<KR, -1, decltype(Pp)::value>(dr, lds, ttr, cr, tr); });
+    __syncthreads();
     static_for<0, KR::E>([&](auto J) {
       constexpr int j = decltype(J)::value;
-      lds[(u * KR::C + cr) * N + ttr + KR::T * j] = dr[u][j];
+      lds[cr * N + ttr + KR::T * j] = dr[j];
+    });
+    __syncthreads();
+    static_for<0, NCT>([&](auto V) {
+      constexpr int v = decltype(V)::value;
+      static_for<0, JR>([&](auto J) {
+        constexpr int j = u * JR + decltype(J)::value;
+        dcl[v][j] = lds[(ttc + KC::T * j - u * KR::C) * N + v * KC::C + cc];
+      });
     });
   });
-  __syncthreads();
-  float2 dcl[NCT][KC::E];
-  static_for<0, NCT>([&](auto U) {
-    constexpr int u = decltype(U)::value;
-    static_for<0, KC::E>([&](auto J) {
-      constexpr int j = decltype(J)::value;
-      dcl[u][j] = lds[(ttc + KC::T * j) * N + u * KC::C + cc];
-    });
-  });
-  __syncthreads();
+  __syncthreads();  // the column passes reuse the LDS
   const float sy = (flags & 2) ? -scale : scale;
-  static_for<0, NCT>([&](auto U) {
-    constexpr int u = decltype(U)::value;
-    static_for<0, KC::P>([&](auto Pp) { run_pass<KC, -1, decltype(Pp)::value>(dcl[u], lds, ttc, cc, tc); });
-    const uint32_t voff = (uint32_t)(ttc * N + u * KC::C + cc) * 8u;
+  static_for<0, NCT>([&](auto V) {
+    constexpr int v = decltype(V)::value;
+    static_for<0, KC::P>([&](auto Pp) { run_pass<KC, -1, decltype(Pp)::value>(dcl[v], lds, ttc, cc, tc); });
+    const uint32_t voff = (uint32_t)(ttc * N + v * KC::C + cc) * 8u;
     static_for<0, KC::E>([&](auto J) {
       constexpr int j = decltype(J)::value;
-      dst.store(make_float2(dcl[u][j].x * scale, dcl[u][j].y * sy), voff, (uint32_t)(KC::T * j * N) * 8u);
+      dst.store(make_float2(dcl[v][j].x * scale, dcl[v][j].y * sy), voff, (uint32_t)(KC::T * j * N) * 8u);
     });
   });
 }
@@ -309,12 +309,15 @@ __device__ __noinline__ __attribute__((flatten)) void grid_item(const float2* in
 __device__ __forceinline__ void run_grid(int rows, int cols, const float2* in, float2* out, const float2* twr,
                                          int twr_count, const float2* twc, int twc_count, int flags, float scale,
                                          float2* lds) {
-  if (rows == 64 && cols == 64)
-    grid_item<BR64, BC64, 64, 64>(in, out, twr, twr_count, twc, twc_count, flags, scale, lds);
-  else if (rows == 64 && cols == 128)
-    grid_item<BR128, BC64, 64, 128>(in, out, twr, twr_count, twc, twc_count, flags, scale, lds);
-  else if (rows == 128 && cols == 64)
-    grid_item<BR64, BC128, 128, 64>(in, out, twr, twr_count, twc, twc_count, flags, scale, lds);
+#define FFT2D_GRID(R, C, KR, KC) \
+  if (rows == R && cols == C) return grid_item<KR, KC, R, C>(in, out, twr, twr_count, twc, twc_count, flags, scale, lds)
+  FFT2D_GRID(64, 64, BR64, BC64);
+  FFT2D_GRID(64, 128, BR128, BC64);
+  FFT2D_GRID(128, 64, BR64, BC128);
+  FFT2D_GRID(128, 128, BR128, BC128);
+  FFT2D_GRID(64, 256, BR256, BC64);
+  FFT2D_GRID(256, 64, BR64, BC256);
+#undef FFT2D_GRID
 }
 
 #define FFT2D_TILE_ARGS in, out, tw, tw_count, rows, cols, m1, t0, cnt, flags, scale, lds
@@ -483,10 +486,11 @@ int ilog2i(int64_t n) {
 // N (512 <= N <= 8192, M1 = its row count) and leaves columns of at most 1024
 // points (tiles of at least 16 columns).
 // Grids done as one whole-grid item (one workgroup, one pass through HBM):
-// the shapes whose row and column configurations cover the grid in whole
-// tiles with at most 16 points per thread (see grid_item).
+// the shapes of at most 16384 points whose row and column configurations
+// cover the grid in whole tiles (see grid_item).
 bool batched_grid_item(int M, int N) {
-  return (M == 64 && N == 64) || (M == 64 && N == 128) || (M == 128 && N == 64);
+  return (M == 64 && (N == 64 || N == 128 || N == 256)) || (N == 64 && (M == 128 || M == 256)) ||
+         (M == 128 && N == 128);
 }
 
 int batched_split(int M, int N) {

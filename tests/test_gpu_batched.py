@@ -104,19 +104,20 @@ def test_batched_split_transforms(F, split, monkeypatch):
 
 @pytest.mark.parametrize("whole", ["auto", "off"])
 def test_batched_whole_grid_items(F, whole, monkeypatch):
-    """64 x 64, 64 x 128 and 128 x 64 grids run as one item each (one pass through
-    HBM) unless FFT2D_BATCH_GRID=off; forward, inverse and in place match the oracle."""
+    """Grids of 64 x 64 ... 128 x 128, 64 x 256 and 256 x 64 run as one item each
+    (one pass through HBM) unless FFT2D_BATCH_GRID=off; forward, inverse and in
+    place match the oracle."""
     import torch
     monkeypatch.setenv("FFT2D_TUNE", "off")
     monkeypatch.setenv("FFT2D_BATCH_GRID", whole)
-    shapes = [(64, 64), (64, 128), (128, 64), (64, 64), (128, 128), (32, 64)] * 3
+    shapes = [(64, 64), (64, 128), (128, 64), (64, 64), (128, 128), (32, 64), (64, 256), (256, 64), (256, 128)] * 2
     say("case batched whole-grid items %s" % whole)
     xs = synth.batched_grids(15, shapes)
     plan = F.BatchedPlan(shapes)
     try:
         desc = plan.describe()
         say(desc)
-        assert (" whole=%d " % (12 if whole == "auto" else 0)) in desc, desc
+        assert (" whole=%d " % (14 if whole == "auto" else 0)) in desc, desc
         ins, ys = _run(F, plan, xs, F.FORWARD)
         _, zs = _run(F, plan, xs, F.INVERSE)
         for x, y, z, s in zip(xs, ys, zs, shapes):
