@@ -19,6 +19,10 @@
  * aligned (16-byte alignment is recommended). Sizes must be powers of two in
  * [1, 16384] per dimension.
  *
+ * Devices: a plan belongs to the HIP device that was current when it was
+ * made; executing it requires that device to be current (and the stream and
+ * data to be on it), else FFT2D_ERR_WRONG_DEVICE.
+ *
  * Streams: `stream` is a hipStream_t passed as void* (NULL = the default
  * stream). fft2d_exec, fft2d_exec_pass and fft2d_backward only enqueue work on
  * that stream; they never synchronise and never allocate, so they can be
@@ -64,7 +68,8 @@ typedef enum fft2d_status {
   FFT2D_ERR_HIP = 7,               /* a HIP runtime call failed; see fft2d_last_error() */
   FFT2D_ERR_INVALID_PLAN = 8,      /* the handle is not a live plan (e.g. already destroyed) */
   FFT2D_ERR_OVERLAP = 9,           /* input and output partially overlap (exact aliasing is allowed) */
-  FFT2D_ERR_INCOMPLETE = 10        /* an earlier fft2d_exec_batched on this plan gave up a bounded wait */
+  FFT2D_ERR_INCOMPLETE = 10,       /* an earlier fft2d_exec_batched on this plan gave up a bounded wait */
+  FFT2D_ERR_WRONG_DEVICE = 11      /* the current HIP device is not the one the plan was made on */
 } fft2d_status;
 
 /* Opaque plan handle, owned by the library until fft2d_destroy(). */

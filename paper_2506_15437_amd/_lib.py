@@ -36,6 +36,7 @@ STATUS_NAMES = {
     8: "FFT2D_ERR_INVALID_PLAN",
     9: "FFT2D_ERR_OVERLAP",
     10: "FFT2D_ERR_INCOMPLETE",
+    11: "FFT2D_ERR_WRONG_DEVICE",
 }
 
 # Every symbol the public header declares.

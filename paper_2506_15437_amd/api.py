@@ -58,6 +58,8 @@ class Plan:
 
     def _check_io(self, x, out):
         _check_tensor(x)
+        if x.device != self.device:
+            raise ValueError("tensor on %s, plan on %s" % (x.device, self.device))
         if x.numel() != self.numel or x.shape[-2:] != (self.rows, self.cols):
             raise ValueError("tensor shape %s does not match plan %dx%dx%d" %
                              (tuple(x.shape), self.batch, self.rows, self.cols))
@@ -71,7 +73,8 @@ class Plan:
         x = x.contiguous()
         if out is None:
             out = torch.empty_like(x)
-        self.exec_ptr(x.data_ptr(), out.data_ptr(), direction, _stream_handle(x.device))
+        with torch.cuda.device(self.device):
+            self.exec_ptr(x.data_ptr(), out.data_ptr(), direction, _stream_handle(x.device))
         return out
 
     def backward(self, g, forward_direction=FORWARD, out=None):
@@ -79,7 +82,8 @@ class Plan:
         g = g.contiguous()
         if out is None:
             out = torch.empty_like(g)
-        self.backward_ptr(g.data_ptr(), out.data_ptr(), forward_direction, _stream_handle(g.device))
+        with torch.cuda.device(self.device):
+            self.backward_ptr(g.data_ptr(), out.data_ptr(), forward_direction, _stream_handle(g.device))
         return out
 
     def describe(self) -> str:
@@ -116,12 +120,19 @@ class BatchedPlan:
             raise ValueError("expected %d tensors, got %d" % (len(self.shapes), len(xs)))
         for i, (x, s) in enumerate(zip(xs, self.shapes)):
             _check_tensor(x, "xs[%d]" % i)
-            if tuple(x.shape) != s or not x.is_contiguous():
-                raise ValueError("xs[%d] must be contiguous with shape %s" % (i, s))
+            if tuple(x.shape) != s or not x.is_contiguous() or x.device != self.device:
+                raise ValueError("xs[%d] must be contiguous with shape %s on %s" % (i, s, self.device))
         if outs is None:
             outs = [torch.empty_like(x) for x in xs]
-        self.exec_ptrs([x.data_ptr() for x in xs], [o.data_ptr() for o in outs], direction,
-                       _stream_handle(xs[0].device))
+        if len(outs) != len(self.shapes):
+            raise ValueError("expected %d output tensors, got %d" % (len(self.shapes), len(outs)))
+        for i, (o, s) in enumerate(zip(outs, self.shapes)):
+            _check_tensor(o, "outs[%d]" % i)
+            if tuple(o.shape) != s or not o.is_contiguous() or o.device != self.device:
+                raise ValueError("outs[%d] must be contiguous with shape %s on %s" % (i, s, self.device))
+        with torch.cuda.device(self.device):
+            self.exec_ptrs([x.data_ptr() for x in xs], [o.data_ptr() for o in outs], direction,
+                           _stream_handle(self.device))
         return outs
 
     def describe(self) -> str:

@@ -249,6 +249,18 @@ void free_plan(fft2d_plan_s* p) {
   delete p;
 }
 
+// Kernels run on the current HIP device; a plan's tables and buffers live on
+// the device that was current when it was made.
+fft2d_status check_device(const fft2d_plan_s* p) {
+  int cur = -1;
+  const hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (cur != p->device)
+    return fail(FFT2D_ERR_WRONG_DEVICE, "the current HIP device is " + std::to_string(cur) + ", the plan's is " +
+                                            std::to_string(p->device));
+  return FFT2D_OK;
+}
+
 fft2d_status check_data_ptrs(const void* in, const void* out, int64_t bytes) {
   if (!in || !out) return fail(FFT2D_ERR_NULL_POINTER, "input or output pointer is NULL");
   if ((reinterpret_cast<uintptr_t>(in) & 7) || (reinterpret_cast<uintptr_t>(out) & 7))
@@ -354,6 +366,7 @@ fft2d_status fft2d_exec(fft2d_plan_t plan, const void* in, void* out, int direct
   if (!plan) return fail(FFT2D_ERR_NULL_POINTER, "plan is NULL");
   if (!is_live(plan)) return fail(FFT2D_ERR_INVALID_PLAN, "plan handle is not live");
   if (plan->kind != kUniform) return fail(FFT2D_ERR_WRONG_PLAN_KIND, "batched plan passed to fft2d_exec");
+  if (fft2d_status dst = check_device(plan); dst != FFT2D_OK) return dst;
   if (direction != FFT2D_FORWARD && direction != FFT2D_INVERSE)
     return fail(FFT2D_ERR_INVALID_DIRECTION, "direction must be FFT2D_FORWARD (-1) or FFT2D_INVERSE (+1)");
   const int64_t bytes = plan->batch * plan->rows * plan->cols * 8;
@@ -368,6 +381,7 @@ fft2d_status fft2d_backward(fft2d_plan_t plan, const void* grad_out, void* grad_
   if (!plan) return fail(FFT2D_ERR_NULL_POINTER, "plan is NULL");
   if (!is_live(plan)) return fail(FFT2D_ERR_INVALID_PLAN, "plan handle is not live");
   if (plan->kind != kUniform) return fail(FFT2D_ERR_WRONG_PLAN_KIND, "batched plan passed to fft2d_backward");
+  if (fft2d_status dst = check_device(plan); dst != FFT2D_OK) return dst;
   if (forward_direction != FFT2D_FORWARD && forward_direction != FFT2D_INVERSE)
     return fail(FFT2D_ERR_INVALID_DIRECTION, "direction must be FFT2D_FORWARD (-1) or FFT2D_INVERSE (+1)");
   const int64_t bytes = plan->batch * plan->rows * plan->cols * 8;
@@ -384,6 +398,7 @@ fft2d_status fft2d_exec_pass(fft2d_plan_t plan, const void* in, void* out, int d
   if (!plan) return fail(FFT2D_ERR_NULL_POINTER, "plan is NULL");
   if (!is_live(plan)) return fail(FFT2D_ERR_INVALID_PLAN, "plan handle is not live");
   if (plan->kind != kUniform) return fail(FFT2D_ERR_WRONG_PLAN_KIND, "batched plan passed to fft2d_exec_pass");
+  if (fft2d_status dst = check_device(plan); dst != FFT2D_OK) return dst;
   if (direction != FFT2D_FORWARD && direction != FFT2D_INVERSE)
     return fail(FFT2D_ERR_INVALID_DIRECTION, "direction must be FFT2D_FORWARD (-1) or FFT2D_INVERSE (+1)");
   if (pass != 0 && pass != 1) return fail(FFT2D_ERR_INVALID_DIRECTION, "pass must be 0 (rows) or 1 (columns)");
@@ -401,6 +416,7 @@ fft2d_status fft2d_exec_batched(fft2d_plan_t plan, const void* const* in, void* 
   if (!plan) return fail(FFT2D_ERR_NULL_POINTER, "plan is NULL");
   if (!is_live(plan)) return fail(FFT2D_ERR_INVALID_PLAN, "plan handle is not live");
   if (plan->kind != kBatched) return fail(FFT2D_ERR_WRONG_PLAN_KIND, "uniform plan passed to fft2d_exec_batched");
+  if (fft2d_status dst = check_device(plan); dst != FFT2D_OK) return dst;
   if (direction != FFT2D_FORWARD && direction != FFT2D_INVERSE)
     return fail(FFT2D_ERR_INVALID_DIRECTION, "direction must be FFT2D_FORWARD (-1) or FFT2D_INVERSE (+1)");
   if (!in || !out) return fail(FFT2D_ERR_NULL_POINTER, "pointer arrays are NULL");
@@ -432,6 +448,7 @@ const char* fft2d_status_string(fft2d_status st) {
     case FFT2D_ERR_INVALID_PLAN: return "invalid plan";
     case FFT2D_ERR_OVERLAP: return "overlapping buffers";
     case FFT2D_ERR_INCOMPLETE: return "incomplete earlier execution";
+    case FFT2D_ERR_WRONG_DEVICE: return "wrong device";
   }
   return "unknown status";
 }

@@ -41,7 +41,7 @@ def test_library_exports_every_declared_symbol(L):
 
 def test_status_strings_and_version(L):
     assert L.status_string(0) == "success"
-    for code in range(1, 11):
+    for code in range(1, 12):
         s = L.status_string(code)
         assert s and s != "unknown status"
     assert L.status_string(99) == "unknown status"

@@ -180,6 +180,10 @@ def test_batched_rejects_bad_input(F, monkeypatch):
         assert e.value.status == 5
         with pytest.raises(ValueError):
             plan([a], F.FORWARD)
+        with pytest.raises(ValueError):
+            plan([a, b], F.FORWARD, [a])  # too few outputs
+        with pytest.raises(ValueError):
+            plan([a, b], F.FORWARD, [a, a])  # an output of the wrong shape
     finally:
         plan.close()
 
