@@ -5,7 +5,7 @@ benchmark's CPU-baseline leg use this module; the product library never
 imports it, and it imports nothing from the product library. It wraps the plain
 C file ``fft_oracle.c`` (built with gcc into ``_oracle.so`` next to it).
 
-Definition followed (the paper computes "the DFT" without writing it; the sign
+Definition followed (the paper computes the discrete Fourier transform without writing it out; the sign
 and normalisation below are this project's reading, pinned by tests against
 closed forms, invariants and a brute-force evaluation):
 

@@ -118,7 +118,7 @@ static int64_t bit_reverse(int64_t v, int bits) {
  *   number of steps log2(n), the loop counter running 0 .. last = log2(n) - 1;
  *   at step s the second point of a pair sits `span` = 2^s after the first
  *   (1, 2, 4 for the three steps of the 8-point example);
- *   there are 2^s distinct twiddles ("spectra") in step s, and pairs with the
+ *   there are 2^s distinct twiddles (the listing's spectra) in step s, and pairs with the
  *   same spectrum repeat every 2^(s+1) points;
  *   the spectrum j uses table entry j << (last - s) of w[q] = W_n^q, q < n/2.
  * Because the butterflies apply the twiddle before the add/subtract with a
