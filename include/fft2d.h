@@ -108,7 +108,7 @@ fft2d_status fft2d_plan(fft2d_plan_t* out, int64_t batch, int64_t rows, int64_t 
  * buffers of the plan's total size, freed before the call returns; if they
  * cannot be allocated the call fails with FFT2D_ERR_OUT_OF_MEMORY (FFT2D_TUNE=off
  * avoids them). The plan also launches a small probe kernel once to learn
- * which XCD each workgroup runs on. Tall grids (rows >= 2048, 512 <= cols <=
+ * which XCD each workgroup runs on. Tall grids (rows >= 1024, 512 <= cols <=
  * 8192) are split as in fft2d_plan: their row pass combines M1 rows into a
  * plan-owned work buffer of rows*cols complex64 each, and their column pass
  * runs columns of rows/M1 points (FFT2D_BATCH_SPLIT=off disables this).

@@ -479,12 +479,6 @@ int ilog2i(int64_t n) {
   return k;
 }
 
-// Split factor of an M x N transform in a batched plan (1 = plain). Column
-// tiles of 2048 or more points per column hold at most 8 columns (64-byte row
-// segments) and are the batched kernel's slowest items; such a transform is
-// split as in the plain path when a row-with-combine configuration exists for
-// N (512 <= N <= 8192, M1 = its row count) and leaves columns of at most 1024
-// points (tiles of at least 16 columns).
 // Grids done as one whole-grid item (one workgroup, one pass through HBM):
 // the shapes of at most 16384 points whose row and column configurations
 // cover the grid in whole tiles (see grid_item).
@@ -493,8 +487,15 @@ bool batched_grid_item(int M, int N) {
          (M == 128 && N == 128);
 }
 
+// Split factor of an M x N transform in a batched plan (1 = plain). Column
+// tiles of 2048 or more points per column hold at most 8 columns (64-byte row
+// segments) and are the batched kernel's slowest items, and 1024-point columns
+// measured faster split too; such a transform is split as in the plain path
+// when a row-with-combine configuration exists for N (512 <= N <= 8192, M1 =
+// its row count) and leaves columns of at most 1024 points (tiles of at least
+// 16 columns).
 int batched_split(int M, int N) {
-  if (M < 2048 || N < 512 || N > 8192) return 1;
+  if (M < 1024 || N < 512 || N > 8192) return 1;
   const PassKernel& k = cfg_table()[32 + ilog2i(N)];
   const int m1 = k.C;
   if (k.L != N || m1 < 2 || M % m1 != 0 || M / m1 > 1024) return 1;
