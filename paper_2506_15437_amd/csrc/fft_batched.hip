@@ -3,8 +3,13 @@
 //
 // Work decomposition. Every transform f (rows M, cols N) becomes row items
 // (tiles of C_row(N) rows; the row FFT of length N) and column items (tiles of
-// C_col(M) columns; the column FFT of length M, in place on the output). A
-// 1 x 1 transform is one copy item.
+// C_col(M) columns; the column FFT of length M, in place on the output); an
+// item is a run of consecutive tiles of one transform and kind. Tall grids
+// are split as in the plain path: their row items are tiles of the row pass
+// with an M1-point combine (into a plan work buffer) and their column items
+// run columns of M / M1 points. Small grids (at most 16384 points, see
+// batched_grid_item) are one whole-grid item each. A 1 x 1 transform is one
+// copy item.
 //
 // Queues. Each transform is assigned to one XCD (balanced by its point
 // count), and each XCD has its own queue of item groups (consecutive items of
