@@ -94,6 +94,24 @@ def test_large_forward(F, shape, seed):
     _check(F, x, -1, "%dx%d fwd" % shape)
 
 
+def test_maximum_grid_16384x16384(F):
+    """The largest supported grid (2^14 per dimension, 2 GiB of complex64):
+    forward against the full FP64 oracle, and the inverse round trip."""
+    import torch
+    say("case 16384x16384 forward + inverse")
+    x = synth.complex_grid(9, (16384, 16384))
+    xd = dev(x)
+    plan = F.get_plan(1, 16384, 16384, "cuda")
+    y = plan(xd, F.FORWARD)
+    err = rel_l2(host(y), oracle.fft2_forward(x))
+    z = plan(y, F.INVERSE)
+    rt = float(torch.linalg.vector_norm(z - xd) / torch.linalg.vector_norm(xd))
+    say("16384x16384 fwd rel_l2=%.3e round trip %.3e" % (err, rt))
+    assert err <= TOL and rt <= TOL
+    del xd, y, z
+    torch.cuda.empty_cache()
+
+
 def test_1d_batch_4096_rows_of_16384(F):
     """rows = 1: a batch of 4096 one-dimensional length-16384 transforms (the
     paper's single-core FFT length, Section 4), forward and inverse; 32 sampled
