@@ -1,0 +1,86 @@
+"""Host-side logic that needs no GPU: argument checks of the Python binding,
+the pointer-array marshalling, and bench.py's rocprofv3 summaries and its
+one-GPU rule."""
+
+from __future__ import annotations
+
+import csv
+import os
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def F():
+    import paper_2506_15437_amd as F
+    return F
+
+
+def test_binding_rejects_bad_tensors_without_a_gpu(F):
+    import torch
+    with pytest.raises(TypeError):
+        F.fft2(np.zeros((4, 4), np.complex64))
+    with pytest.raises(TypeError):
+        F.fft2(torch.zeros(4, 4, dtype=torch.complex64))  # host tensor
+    with pytest.raises(TypeError):
+        F.fft2(torch.zeros(4, 4, dtype=torch.float32))
+
+
+def test_pointer_array(F):
+    a = F.pointer_array([0x1000, 0x2008, 2**40])
+    assert a.dtype == np.uint64 and a.tolist() == [0x1000, 0x2008, 2**40]
+    assert F.pointer_array(a) is a  # an array of the right type passes through unconverted
+
+
+def _write_counters(path, rows):
+    os.makedirs(path, exist_ok=True)
+    with open(os.path.join(path, "run_counter_collection.csv"), "w", newline="") as fh:
+        w = csv.writer(fh)
+        w.writerow(["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
+        for r in rows:
+            w.writerow(r)
+
+
+def test_traffic_summary_scales_by_the_copy(tmp_path, monkeypatch):
+    """FETCH_SIZE reading half of a copy's bytes gives a factor of 2; the
+    per-pass figure is the scaled sum, dispatches assigned in step order."""
+    import bench
+    grid = 4096 * 4096 * 8  # bytes of one grid
+    kib = grid / 1024
+    names = ["fft2d::dev::rowc_kernel<a, -1>", "fft2d::dev::pass_kernel<b, -1>",
+             "fft2d::dev::rowc_kernel<a, 1>", "fft2d::dev::pass_kernel<b, 1>"]
+    fetch, write = [], []
+    for step in range(2):
+        for i, n in enumerate(names):
+            d = 10 + step * 4 + i
+            fetch.append([d, n, "FETCH_SIZE", kib / 2 * (1.05 if i == 0 else 1.0)])
+            write.append([d, n, "WRITE_SIZE", kib])
+    _write_counters(tmp_path / "f", fetch + [[1, "some_other_kernel", "FETCH_SIZE", 1.0]])
+    _write_counters(tmp_path / "w", write)
+    _write_counters(tmp_path / "cf", [[1, "__amd_rocclr_copyBuffer", "FETCH_SIZE", kib / 2]])
+    _write_counters(tmp_path / "cw", [[1, "__amd_rocclr_copyBuffer", "WRITE_SIZE", kib]])
+    text = bench.summarize_traffic(str(tmp_path / "f"), str(tmp_path / "w"), str(tmp_path / "cf"),
+                                   str(tmp_path / "cw"))
+    lines = {l.split()[1]: l.split() for l in text.splitlines() if l.startswith("pass ")}
+    assert "fetch_factor = 2.0000" in text and "write_factor = 1.0000" in text
+    assert int(lines["fwd_row"][3]) == round(grid * 1.05) + grid
+    assert int(lines["fwd_col"][3]) == 2 * grid
+    assert lines["inv_col"][-1].endswith("1>")
+    # the bench reads the figure back only while the source hash matches
+    prof = tmp_path / "profile.txt"
+    prof.write_text("# header\n" + text + "\n")
+    monkeypatch.setattr(bench, "TRAFFIC_PROFILE", str(prof))
+    assert bench.measured_traffic("fwd_col") == 2 * grid
+    prof.write_text(text.replace(bench.kernel_source_hash(), "0" * 16))
+    assert bench.measured_traffic("fwd_col") is None
+
+
+def test_bench_refuses_more_than_one_gpu():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
