@@ -6,6 +6,7 @@ tensor's current torch stream; nothing here synchronises.
 
 from __future__ import annotations
 
+import collections
 import threading
 
 import torch
@@ -90,9 +91,18 @@ class Plan:
         return _lib.fft2d_plan_describe(self.handle)
 
     def close(self):
+        """Free the plan. The C call waits for nothing, so the plan's device is
+        synchronised first: no queued work may still use the plan's memory."""
         if getattr(self, "handle", None):
+            torch.cuda.synchronize(self.device)
             _lib.fft2d_destroy(self.handle)
             self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # interpreter shutdown: the library may already be gone
+            pass
 
 
 class BatchedPlan:
@@ -139,17 +149,30 @@ class BatchedPlan:
         return _lib.fft2d_plan_describe(self.handle)
 
     def close(self):
+        """Free the plan. The C call waits for nothing, so the plan's device is
+        synchronised first: no queued work may still use the plan's memory."""
         if getattr(self, "handle", None):
+            torch.cuda.synchronize(self.device)
             _lib.fft2d_destroy(self.handle)
             self.handle = None
 
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # interpreter shutdown: the library may already be gone
+            pass
 
-_plans = {}
+
+_plans = collections.OrderedDict()
 _plans_lock = threading.Lock()
 
 
+PLAN_CACHE_SIZE = 32  # plans kept by get_plan (least recently used evicted beyond this)
+
+
 def get_plan(batch: int, rows: int, cols: int, device) -> Plan:
-    """Cached uniform plan for (device, batch, rows, cols)."""
+    """Cached uniform plan for (device, batch, rows, cols). At most PLAN_CACHE_SIZE
+    plans are kept; an evicted plan is freed when its last reference goes."""
     dev = torch.device(device)
     key = (dev.index if dev.index is not None else torch.cuda.current_device(), int(batch), int(rows), int(cols))
     with _plans_lock:
@@ -157,7 +180,17 @@ def get_plan(batch: int, rows: int, cols: int, device) -> Plan:
         if p is None:
             p = Plan(batch, rows, cols, device=torch.device("cuda", key[0]))
             _plans[key] = p
+            while len(_plans) > PLAN_CACHE_SIZE:
+                _plans.popitem(last=False)
+        else:
+            _plans.move_to_end(key)
         return p
+
+
+def clear_plan_cache() -> None:
+    """Forget every plan cached by get_plan (each is freed with its last reference)."""
+    with _plans_lock:
+        _plans.clear()
 
 
 def _plan_for(x) -> Plan:
