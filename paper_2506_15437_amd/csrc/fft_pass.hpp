@@ -15,9 +15,10 @@
 //   * between passes, the points are multiplied by the inter-pass twiddles
 //     W_{Ns R}^{k r} (FP32 table, computed in FP64 on the host) and written
 //     back through LDS directly into the order the next pass reads (a Stockham
-//     auto-sort), which is the paper's "one data reordering per step" idea
-//     (Section 4, Fig. 5) moved on-chip: the digit reversal of the whole
-//     transform costs no HBM traffic at all.
+//     auto-sort). The paper makes the same move on the Tensix (Section 4,
+//     Fig. 5): each step reorders straight into the next step's order rather
+//     than back to the natural order. Here that reordering happens on-chip,
+//     so the digit reversal of the whole transform costs no HBM traffic.
 // Each pass kernel therefore reads every point from HBM once, coalesced, and
 // writes it once, coalesced (first pass loads point tt + T*j into register j,
 // the last pass stores register j to point tt + T*j).
