@@ -32,8 +32,9 @@
  * not meant to be captured.
  *
  * Errors: every function returns an fft2d_status and never throws. On failure
- * nothing is enqueued, outputs are untouched, and fft2d_last_error() gives a
- * thread-local detail string.
+ * nothing is enqueued (except after a failed launch of a batch above 2^31
+ * points, see fft2d_plan), outputs are untouched, and fft2d_last_error() gives
+ * a thread-local detail string.
  *
  * Thread safety: a plain uniform plan is read-only during execution and may be
  * used from several host threads and streams at once. A split plan (large
@@ -90,8 +91,15 @@ typedef struct fft2d_plan_s* fft2d_plan_t;
  * pass also applies the first M1-point stage of the column FFT, the column pass
  * the remaining length-M2 stage), which needs a plan-owned work buffer of
  * batch*rows*cols complex64 points; the environment variable FFT2D_SPLIT
- * (off | auto | M1) overrides the choice at plan time. Must be called with a
- * GPU present.
+ * (off | auto | M1) overrides the choice at plan time. Grids of 64 x 64,
+ * 64 x 128, 128 x 64, 128 x 128, 64 x 256 and 256 x 64 run both passes in one
+ * whole-grid launch (one workgroup per grid, every point read and written
+ * once) when the batch is large enough to fill the GPU (any batch for 64 x 64,
+ * at least 32 grids of 8192 points, 128 grids of 16384 points); FFT2D_GRID
+ * (off | auto | on) overrides that choice. Batches of more than 2^31 points run
+ * as several launches of whole grids (a HIP launch holds fewer than 2^32
+ * work-items); if one of those launches fails, the earlier ones stay enqueued.
+ * Must be called with a GPU present.
  */
 fft2d_status fft2d_plan(fft2d_plan_t* out, int64_t batch, int64_t rows, int64_t cols);
 
@@ -166,7 +174,9 @@ fft2d_status fft2d_backward(fft2d_plan_t plan, const void* grad_out, void* grad_
  * transform), pass 1 the column pass. Pass 0 reads `in` and writes the
  * intermediate result; pass 1 reads the intermediate and writes `out`. The
  * intermediate is the plan's work buffer for split plans and `out` otherwise,
- * so pass 0 then pass 1 with the same arguments is exactly fft2d_exec. The
+ * so pass 0 then pass 1 with the same arguments is exactly fft2d_exec (for a
+ * plan that runs the whole-grid kernel: the same transform in two launches,
+ * equal to it up to rounding). The
  * inverse's 1/(M N) scale is applied by the last pass. Returns
  * FFT2D_ERR_INVALID_SIZE if the plan has no such pass (that dimension has
  * length 1) and FFT2D_ERR_INVALID_DIRECTION for a pass index other than 0 or 1.

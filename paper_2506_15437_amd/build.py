@@ -17,8 +17,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OBJDIR = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libfft2d.so")
-SOURCES = ["fft_kernels_row.hip", "fft_kernels_col.hip", "fft_kernels_split.hip", "fft_kernels.hip",
-           "fft_batched.hip", "fft2d.cpp"]
+SOURCES = ["fft_kernels_row.hip", "fft_kernels_col.hip", "fft_kernels_split.hip", "fft_kernels_grid.hip",
+           "fft_kernels.hip", "fft_batched.hip", "fft2d.cpp"]
 ARCH = "gfx950"
 
 # Packed FP32 instructions are kept out of the generated code on purpose.

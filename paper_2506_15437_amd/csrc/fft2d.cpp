@@ -67,6 +67,27 @@ int64_t choose_split(int64_t rows, int64_t cols) {
   return usable(16384 / cols) ? 16384 / cols : 1;
 }
 
+// Whether a plan of `batch` grids of `points` points runs the whole-grid
+// kernel (one workgroup per grid) rather than the two passes, which spread
+// each grid over many workgroups. Measured crossover on MI355X: grids of 4096
+// points gain at any batch, grids of 8192 points from about 32 grids, grids of
+// 16384 points from about 128. FFT2D_GRID=on|off overrides (default auto).
+bool use_grid_kernel(int64_t batch, int64_t points) {
+  const char* env = std::getenv("FFT2D_GRID");
+  if (env && std::strcmp(env, "off") == 0) return false;
+  if (env && std::strcmp(env, "on") == 0) return true;
+  const int64_t min_batch = points <= 4096 ? 1 : points <= 8192 ? 32 : 128;
+  return batch >= min_batch;
+}
+
+// Same FFT length and radix sequence (hence the same twiddle table).
+bool same_schedule(const PassKernel& a, const PassKernel& b) {
+  if (a.L != b.L || a.npass != b.npass) return false;
+  for (int i = 0; i < a.npass; ++i)
+    if (a.radix[i] != b.radix[i]) return false;
+  return true;
+}
+
 }  // namespace
 
 struct fft2d_plan_s {
@@ -79,6 +100,9 @@ struct fft2d_plan_s {
   int64_t m1 = 1, m2 = 0;
   const PassKernel* row_k = nullptr;  // length-cols FFT along rows (null if cols == 1)
   const PassKernel* col_k = nullptr;  // length-rows (or m2) FFT down columns (null if rows == 1)
+  // Small grids: both passes in one whole-grid launch (same radix schedules
+  // and tables as row_k / col_k, which fft2d_exec_pass still runs).
+  const GridKernel* grid_k = nullptr;
   float2* tw_row = nullptr;
   float2* tw_col = nullptr;
   float2* tw_comb = nullptr;  // W_rows^j, j < rows (split transforms)
@@ -149,42 +173,57 @@ hipError_t upload_root_table(int64_t n, float2** dev) {
   return e;
 }
 
-// Enqueue the row pass then the column pass of `batch` grids of rows x cols
-// (only_pass = 0 or 1 restricts it to one of them).
-fft2d_status run_uniform(const fft2d_plan_s* p, const float2* in, float2* out, int sign, float scale,
-                         hipStream_t s, int only_pass = -1) {
-  const int64_t npts = p->batch * p->rows * p->cols;
+// Enqueue the transform of nb consecutive grids of rows x cols (in, out and
+// work point at the first of them): the whole-grid kernel, or the row pass then
+// the column pass (only_pass = 0 or 1 restricts it to one of them).
+fft2d_status run_grids(const fft2d_plan_s* p, int64_t nb, const float2* in, float2* out, float2* work, int sign,
+                       float scale, hipStream_t s, int only_pass) {
+  const int64_t npts = nb * p->rows * p->cols;
   hipError_t e;
   if (!p->row_k && !p->col_k) {
     e = launch_scale_copy(in, out, npts, scale, s);
     return e == hipSuccess ? FFT2D_OK : hip_fail(e, "scale copy launch");
   }
+  if (p->grid_k && only_pass < 0) {
+    PassArgs a{};
+    a.in = in;
+    a.out = out;
+    a.tw = p->tw_row;
+    a.tw_count = (int64_t)twiddle_count(*p->row_k);
+    a.twc = p->tw_col;
+    a.total = npts;
+    a.nvec = nb;
+    a.scale = scale;
+    a.nblocks = (int)nb;
+    e = p->grid_k->launch(a, sign, s);
+    return e == hipSuccess ? FFT2D_OK : hip_fail(e, "whole-grid kernel launch");
+  }
   if (p->m1 > 1) {
     if (only_pass != 1) {
       PassArgs a{};
       a.in = in;
-      a.out = p->work;
+      a.out = work;
       a.tw = p->tw_row;
       a.tw_count = (int64_t)twiddle_count(*p->row_k);
       a.total = npts;
       a.twc = p->tw_comb;
-      a.nvec = p->batch * p->rows;
+      a.nvec = nb * p->rows;
       a.ncols = p->cols;
       a.m1 = p->m1;
       a.m2 = p->m2;
       a.scale = 1.0f;
-      a.nblocks = (int)(p->batch * p->m2);
+      a.nblocks = (int)(nb * p->m2);
       e = p->row_k->launch(a, sign, s);
       if (e != hipSuccess) return hip_fail(e, "row pass (combine) launch");
     }
     if (only_pass != 0) {
       PassArgs a{};
-      a.in = p->work;
+      a.in = work;
       a.out = out;
       a.tw = p->tw_col;
       a.tw_count = (int64_t)twiddle_count(*p->col_k);
       a.total = npts;
-      a.nvec = p->batch * p->m1 * p->cols;
+      a.nvec = nb * p->m1 * p->cols;
       a.ncols = p->cols;
       a.m1 = p->m1;
       a.m2 = p->m2;
@@ -203,7 +242,7 @@ fft2d_status run_uniform(const fft2d_plan_s* p, const float2* in, float2* out, i
     a.tw = p->tw_row;
     a.tw_count = (int64_t)twiddle_count(*p->row_k);
     a.total = npts;
-    a.nvec = p->batch * p->rows;
+    a.nvec = nb * p->rows;
     a.ncols = p->cols;
     a.m1 = 1;
     a.scale = p->col_k ? 1.0f : scale;
@@ -219,13 +258,33 @@ fft2d_status run_uniform(const fft2d_plan_s* p, const float2* in, float2* out, i
     a.tw = p->tw_col;
     a.tw_count = (int64_t)twiddle_count(*p->col_k);
     a.total = npts;
-    a.nvec = p->batch * p->cols;
+    a.nvec = nb * p->cols;
     a.ncols = p->cols;
     a.m1 = 1;
     a.scale = scale;
     a.nblocks = pass_blocks(*p->col_k, a.nvec);
     e = p->col_k->launch(a, sign, s);
     if (e != hipSuccess) return hip_fail(e, "column pass launch");
+  }
+  return FFT2D_OK;
+}
+
+// Points one launch covers at most. Every kernel runs at least two points per
+// thread, so a launch stays below 2^30 work-items (a HIP grid dimension holds
+// fewer than 2^32); larger batches run as several launches of whole grids.
+constexpr int64_t kMaxLaunchPoints = int64_t(1) << 31;
+
+// Enqueue the transform of the plan's whole batch.
+fft2d_status run_uniform(const fft2d_plan_s* p, const float2* in, float2* out, int sign, float scale,
+                         hipStream_t s, int only_pass = -1) {
+  const int64_t per = p->rows * p->cols;
+  const int64_t chunk = std::max<int64_t>(1, kMaxLaunchPoints / per);
+  for (int64_t b0 = 0; b0 < p->batch; b0 += chunk) {
+    const int64_t nb = std::min(chunk, p->batch - b0);
+    const int64_t off = b0 * per;
+    const fft2d_status st =
+        run_grids(p, nb, in + off, out + off, p->work ? p->work + off : nullptr, sign, scale, s, only_pass);
+    if (st != FFT2D_OK) return st;
   }
   return FFT2D_OK;
 }
@@ -305,6 +364,10 @@ fft2d_status fft2d_plan(fft2d_plan_t* out, int64_t batch, int64_t rows, int64_t 
   } else {
     if (cols > 1) p->row_k = find_pass_kernel((int)cols, false);
     if (rows > 1) p->col_k = find_pass_kernel((int)rows, true);
+    const GridKernel* g = find_grid_kernel((int)rows, (int)cols);
+    if (g && p->row_k && p->col_k && same_schedule(g->row, *p->row_k) && same_schedule(g->col, *p->col_k) &&
+        use_grid_kernel(batch, rows * cols))
+      p->grid_k = g;
   }
   if ((cols > 1 && !p->row_k) || (rows > 1 && !p->col_k)) {
     delete p;
@@ -471,7 +534,11 @@ fft2d_status fft2d_plan_describe(fft2d_plan_t plan, char* buf, int64_t buflen) {
   };
   if (plan->kind == kUniform) {
     d = "uniform batch=" + std::to_string(plan->batch) + " " + std::to_string(plan->rows) + "x" +
-        std::to_string(plan->cols) + " split=" + std::to_string(plan->m1) + " row[" + desc(plan->row_k) +
+        std::to_string(plan->cols) + " split=" + std::to_string(plan->m1) +
+        (plan->grid_k ? " grid[threads=" + std::to_string(plan->grid_k->threads) +
+                            " lds=" + std::to_string(plan->grid_k->lds_bytes) + "]"
+                      : std::string()) +
+        " row[" + desc(plan->row_k) +
         (plan->m1 > 1 ? " combine" : "") + "] col[" + desc(plan->col_k) + "]";
   } else {
     d = describe_batched(plan->batched);

@@ -255,59 +255,19 @@ template <class KR, class KC, int M, int N>
 __device__ __noinline__ __attribute__((flatten)) void grid_item(const float2* in, float2* out, const float2* twr,
                                                                 int twr_count, const float2* twc, int twc_count,
                                                                 int flags, float scale, float2* lds) {
-  static_assert(!KR::COL && KC::COL && KR::L == N && KC::L == M, "row and column configurations of the grid");
+  static_assert(KR::L == N && KC::L == M, "row and column configurations of the grid");
   static_assert(KR::THREADS == kThreads && KC::THREADS == kThreads, "batched configurations use 512 threads");
-  static_assert(M % KR::C == 0 && N % KC::C == 0, "whole tiles");
-  static_assert(KR::C % KC::T == 0 && KR::C * N <= kLdsElems, "a row tile holds whole point blocks, fits the LDS");
-  constexpr int NRT = M / KR::C;
-  constexpr int NCT = N / KC::C;
-  constexpr int JR = KR::C / KC::T;  // column points j of row tile u: u * JR <= j < (u + 1) * JR
+  static_assert(grid_lds_elems<KR, KC>() <= kLdsElems, "the grid's row tile fits the LDS");
   const Buf src(uniform(in), (uint32_t)(M * N) * 8u);
   const Buf dst(uniform(out), (uint32_t)(M * N) * 8u);
   const Buf tr(uniform(twr), (uint32_t)uniform(twr_count) * 8u);
   const Buf tc(uniform(twc), (uint32_t)uniform(twc_count) * 8u);
   flags = uniform(flags);
-  scale = uniform(scale);
-  const int t = threadIdx.x;
-  const int cr = t / KR::T, ttr = t % KR::T;  // row tiles: row cr of the tile, points ttr + T j
-  const int cc = t % KC::C, ttc = t / KC::C;  // column tiles: column cc of the tile, points ttc + T j
-  float2 dcl[NCT][KC::E];
-  static_for<0, NRT>([&](auto U) {
-    constexpr int u = decltype(U)::value;
-    float2 dr[KR::E];
-    const uint32_t voff = (uint32_t)((u * KR::C + cr) * N + ttr) * 8u;
-    static_for<0, KR::E>([&](auto J) {
-      constexpr int j = decltype(J)::value;
-      dr[j] = src.load(voff, (uint32_t)(KR::T * j) * 8u);
-      if (flags & 1) dr[j].y = -dr[j].y;
-    });
-    if constexpr (u > 0) __syncthreads();  // the previous row tile's points have been read from LDS
-    static_for<0, KR::P>([&](auto Pp) { run_pass<KR, -1, decltype(Pp)::value>(dr, lds, ttr, cr, tr); });
-    __syncthreads();
-    static_for<0, KR::E>([&](auto J) {
-      constexpr int j = decltype(J)::value;
-      lds[cr * N + ttr + KR::T * j] = dr[j];
-    });
-    __syncthreads();
-    static_for<0, NCT>([&](auto V) {
-      constexpr int v = decltype(V)::value;
-      static_for<0, JR>([&](auto J) {
-        constexpr int j = u * JR + decltype(J)::value;
-        dcl[v][j] = lds[(ttc + KC::T * j - u * KR::C) * N + v * KC::C + cc];
-      });
-    });
-  });
-  __syncthreads();  // the column passes reuse the LDS
-  const float sy = (flags & 2) ? -scale : scale;
-  static_for<0, NCT>([&](auto V) {
-    constexpr int v = decltype(V)::value;
-    static_for<0, KC::P>([&](auto Pp) { run_pass<KC, -1, decltype(Pp)::value>(dcl[v], lds, ttc, cc, tc); });
-    const uint32_t voff = (uint32_t)(ttc * N + v * KC::C + cc) * 8u;
-    static_for<0, KC::E>([&](auto J) {
-      constexpr int j = decltype(J)::value;
-      dst.store(make_float2(dcl[v][j].x * scale, dcl[v][j].y * sy), voff, (uint32_t)(KC::T * j * N) * 8u);
-    });
-  });
+  TileIO io;
+  io.conj_in = (flags & 1) != 0;
+  io.conj_out = (flags & 2) != 0;
+  io.scale = uniform(scale);
+  grid_tile<KR, KC, -1>(src, dst, tr, tc, io, lds);
 }
 
 // The grids handled as whole-grid items (see batched_grid_item on the host).

@@ -52,12 +52,25 @@ struct PassKernel {
   hipError_t (*launch)(const PassArgs&, int dir, hipStream_t);
 };
 
+// One compiled whole-grid kernel: the 2D transform of `rows` x `cols` grids,
+// one workgroup per grid. Launch with PassArgs in/out/total, nvec = nblocks =
+// number of grids, tw = the row schedule's table, twc = the column schedule's
+// table, scale.
+struct GridKernel {
+  int rows, cols, threads;
+  PassKernel row, col;  // shapes (radix schedules) of its row and column FFTs
+  size_t lds_bytes;
+  hipError_t (*launch)(const PassArgs&, int dir, hipStream_t);
+};
+
 // Default kernel for a length L in [2, 16384] (power of two); nullptr otherwise.
 const PassKernel* find_pass_kernel(int L, bool colmode);
 // Row pass with an M1-point combine across M1 rows of length L (nullptr if none).
 const PassKernel* find_combine_kernel(int L, int m1);
 // Column pass for the length-M2 columns of a split transform.
 const PassKernel* find_split_column_kernel(int L);
+// Whole-grid kernel for rows x cols grids (nullptr if none).
+const GridKernel* find_grid_kernel(int rows, int cols);
 // All compiled variants for a length (for the autotuner); returns the count.
 int list_pass_kernels(int L, bool colmode, const PassKernel** out, int cap);
 

@@ -42,6 +42,14 @@ const PassKernel* find_split_column_kernel(int L) {
   return nullptr;
 }
 
+const GridKernel* find_grid_kernel(int rows, int cols) {
+  int n = 0;
+  const GridKernel* tab = grid_kernel_table(&n);
+  for (int i = 0; i < n; ++i)
+    if (tab[i].rows == rows && tab[i].cols == cols) return &tab[i];
+  return nullptr;
+}
+
 int list_pass_kernels(int L, bool colmode, const PassKernel** out, int cap) {
   const PassKernel* k = find_pass_kernel(L, colmode);
   if (!k) return 0;

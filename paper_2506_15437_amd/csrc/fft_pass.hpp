@@ -523,6 +523,91 @@ __global__ __launch_bounds__(K::THREADS) __attribute__((amdgpu_waves_per_eu(WPE)
   rowc_tile<K, DIR, NT ? kAuxNontemporal : 0, SB>(a, blockIdx.x, lds, TileIO{});
 }
 
+// Whole-grid tile: one workgroup computes the complete 2D transform of one
+// M x N grid (M = KC::L rows, N = KR::L columns), reading and writing every
+// point once. Row tiles of KR::C rows are loaded and transformed in turn; each
+// passes through the LDS, where every thread picks up the points of the
+// columns it owns in KC's layout (column v*KC::C + cc, points ttc + KC::T*j)
+// and keeps them in registers; then the columns are transformed and stored.
+// src/dst cover the grid (row-major, N contiguous); tr/tc are the twiddle
+// tables of KR's and KC's schedules.
+template <class KR, class KC>
+constexpr int grid_lds_elems() {
+  int m = KR::LDS_ELEMS > KC::LDS_ELEMS ? KR::LDS_ELEMS : KC::LDS_ELEMS;
+  return KR::C * KR::L > m ? KR::C * KR::L : m;
+}
+
+template <class KR, class KC, int DIR>
+__device__ __forceinline__ void grid_tile(const Buf& src, const Buf& dst, const Buf& tr, const Buf& tc, TileIO io,
+                                          float2* lds) {
+  constexpr int M = KC::L;
+  constexpr int N = KR::L;
+  static_assert(KR::valid() && KC::valid() && !KR::COL && KC::COL, "row and column configurations");
+  static_assert(KR::THREADS == KC::THREADS, "one workgroup runs both");
+  static_assert(M % KR::C == 0 && N % KC::C == 0, "whole tiles");
+  static_assert(KR::C % KC::T == 0, "a row tile holds whole point blocks of the column layout");
+  constexpr int NRT = M / KR::C;
+  constexpr int NCT = N / KC::C;
+  constexpr int JR = KR::C / KC::T;  // column points j of row tile u: u * JR <= j < (u + 1) * JR
+  const int t = threadIdx.x;
+  const int cr = t / KR::T, ttr = t % KR::T;  // row tiles: row cr of the tile, points ttr + T j
+  const int cc = t % KC::C, ttc = t / KC::C;  // column tiles: column cc of the tile, points ttc + T j
+  float2 dcl[NCT][KC::E];
+  static_for<0, NRT>([&](auto U) {
+    constexpr int u = decltype(U)::value;
+    float2 dr[KR::E];
+    const uint32_t voff = (uint32_t)((u * KR::C + cr) * N + ttr) * 8u;
+    static_for<0, KR::E>([&](auto J) {
+      constexpr int j = decltype(J)::value;
+      dr[j] = src.load(voff, (uint32_t)(KR::T * j) * 8u);
+      if (io.conj_in) dr[j].y = -dr[j].y;
+    });
+    if constexpr (u > 0) __syncthreads();  // the previous row tile's points have been read from LDS
+    static_for<0, KR::P>([&](auto Pp) { run_pass<KR, DIR, decltype(Pp)::value>(dr, lds, ttr, cr, tr); });
+    __syncthreads();
+    static_for<0, KR::E>([&](auto J) {
+      constexpr int j = decltype(J)::value;
+      lds[cr * N + ttr + KR::T * j] = dr[j];
+    });
+    __syncthreads();
+    static_for<0, NCT>([&](auto V) {
+      constexpr int v = decltype(V)::value;
+      static_for<0, JR>([&](auto J) {
+        constexpr int j = u * JR + decltype(J)::value;
+        dcl[v][j] = lds[(ttc + KC::T * j - u * KR::C) * N + v * KC::C + cc];
+      });
+    });
+  });
+  __syncthreads();  // the column passes reuse the LDS
+  const float sc = io.scale;
+  const float sy = io.conj_out ? -sc : sc;
+  static_for<0, NCT>([&](auto V) {
+    constexpr int v = decltype(V)::value;
+    static_for<0, KC::P>([&](auto Pp) { run_pass<KC, DIR, decltype(Pp)::value>(dcl[v], lds, ttc, cc, tc); });
+    const uint32_t voff = (uint32_t)(ttc * N + v * KC::C + cc) * 8u;
+    static_for<0, KC::E>([&](auto J) {
+      constexpr int j = decltype(J)::value;
+      dst.store(make_float2(dcl[v][j].x * sc, dcl[v][j].y * sy), voff, (uint32_t)(KC::T * j * N) * 8u);
+    });
+  });
+}
+
+// Whole-grid kernel: workgroup g transforms grid g of the batch (a.nvec grids
+// of KC::L x KR::L; a.tw = KR's table, a.twc = KC's table).
+template <class KR, class KC, int DIR>
+__global__ __launch_bounds__(KR::THREADS) void grid_kernel(PassArgs a) {
+  __shared__ float2 lds[grid_lds_elems<KR, KC>()];
+  constexpr int64_t P = (int64_t)KR::L * KC::L;
+  const int64_t base = (int64_t)blockIdx.x * P;
+  const Buf src(a.in + base, span_bytes(a.total, base));
+  const Buf dst(a.out + base, span_bytes(a.total, base));
+  const Buf tr(a.tw, (uint32_t)KR::tw_off(KR::P) * 8u);
+  const Buf tc(a.twc, (uint32_t)KC::tw_off(KC::P) * 8u);
+  TileIO io;
+  io.scale = a.scale;
+  grid_tile<KR, KC, DIR>(src, dst, tr, tc, io, lds);
+}
+
 template <class K, int WPE, bool NT>
 hipError_t launch_pass(const PassArgs& a, int dir, hipStream_t s) {
   if (dir < 0) hipLaunchKernelGGL((pass_kernel<K, -1, NT, WPE>), dim3(a.nblocks), dim3(K::THREADS), 0, s, a);
