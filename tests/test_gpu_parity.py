@@ -138,7 +138,8 @@ def test_1d_batch_4096_rows_of_16384(F):
     assert worst <= TOL and parseval <= 1e-5 and rt <= TOL
 
 
-@pytest.mark.parametrize("shape", [(256, 512), (4096, 1024)], ids=["256x512", "4096x1024-split"])
+@pytest.mark.parametrize("shape", [(64, 64), (256, 512), (4096, 1024)], ids=["64x64-whole-grid", "256x512",
+                                                                          "4096x1024-split"])
 def test_exec_captured_in_hip_graph(F, shape):
     """fft2d_exec enqueues kernels only, so it can be captured in a HIP graph
     (torch.cuda.CUDAGraph); every replay, with eager work between replays,
