@@ -91,11 +91,12 @@ typedef struct fft2d_plan_s* fft2d_plan_t;
  * pass also applies the first M1-point stage of the column FFT, the column pass
  * the remaining length-M2 stage), which needs a plan-owned work buffer of
  * batch*rows*cols complex64 points; the environment variable FFT2D_SPLIT
- * (off | auto | M1) overrides the choice at plan time. Grids of 64 x 64,
- * 64 x 128, 128 x 64, 128 x 128, 64 x 256 and 256 x 64 run both passes in one
- * whole-grid launch (one workgroup per grid, every point read and written
- * once) when the batch is large enough to fill the GPU (any batch for 64 x 64,
- * at least 32 grids of 8192 points, 128 grids of 16384 points); FFT2D_GRID
+ * (off | auto | M1) overrides the choice at plan time. Grids of 32 x 32,
+ * 32 x 64, 64 x 32, 64 x 64, 32 x 128, 128 x 32, 64 x 128, 128 x 64, 128 x 128,
+ * 32 x 256, 256 x 32, 64 x 256 and 256 x 64 run both passes in one whole-grid
+ * launch (one workgroup per grid, every point read and written once) when the
+ * batch is large enough to fill the GPU (any batch for grids of up to 4096
+ * points, at least 32 grids of 8192 points, 128 grids of 16384); FFT2D_GRID
  * (off | auto | on) overrides that choice. Batches of more than 2^31 points run
  * as several launches of whole grids (a HIP launch holds fewer than 2^32
  * work-items); if one of those launches fails, the earlier ones stay enqueued.

@@ -13,7 +13,8 @@ from tests.gpu_util import TOL, dev, host, rel_l2, say
 
 pytestmark = pytest.mark.gpu
 
-GRID_SHAPES = [(64, 64), (64, 128), (128, 64), (128, 128), (64, 256), (256, 64)]
+GRID_SHAPES = [(64, 64), (64, 128), (128, 64), (128, 128), (64, 256), (256, 64), (32, 32), (32, 64), (64, 32),
+               (32, 128), (128, 32), (32, 256), (256, 32)]
 
 
 @pytest.fixture(scope="module")
@@ -70,7 +71,9 @@ def test_whole_grid_kernel(F, shape, batch, monkeypatch):
 
 @pytest.mark.parametrize("shape,batch,expected", [((64, 64), 1, True), ((64, 128), 31, False),
                                                   ((64, 128), 32, True), ((128, 128), 127, False),
-                                                  ((256, 64), 128, True), ((256, 256), 1000, False)])
+                                                  ((256, 64), 128, True), ((256, 256), 1000, False),
+                                                  ((32, 32), 1, True), ((32, 256), 31, False), ((256, 32), 32, True),
+                                                  ((16, 16), 1000, False), ((32, 512), 1000, False)])
 def test_whole_grid_choice(F, shape, batch, expected, monkeypatch):
     """By default small batches of the larger grids keep the two passes."""
     say("case whole-grid choice b%d %dx%d" % ((batch,) + shape))
