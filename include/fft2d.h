@@ -91,7 +91,9 @@ typedef struct fft2d_plan_s* fft2d_plan_t;
  * pass also applies the first M1-point stage of the column FFT, the column pass
  * the remaining length-M2 stage), which needs a plan-owned work buffer of
  * batch*rows*cols complex64 points; the environment variable FFT2D_SPLIT
- * (off | auto | M1) overrides the choice at plan time. Grids of 32 x 32,
+ * (off | auto | M1) overrides the choice at plan time, FFT2D_SPLIT_COLUMN
+ * (narrow | auto | wide) the column kernel's points per thread (32 | 64; auto
+ * takes 64 where there is such a kernel and cols >= 4096). Grids of 32 x 32,
  * 32 x 64, 64 x 32, 64 x 64, 32 x 128, 128 x 32, 64 x 128, 128 x 64, 128 x 128,
  * 32 x 256, 256 x 32, 64 x 256 and 256 x 64 run both passes in one whole-grid
  * launch (one workgroup per grid, every point read and written once) when the

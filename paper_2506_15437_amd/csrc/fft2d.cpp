@@ -80,6 +80,19 @@ bool use_grid_kernel(int64_t batch, int64_t points) {
   return batch >= min_batch;
 }
 
+// Whether a split plan's column pass uses the 64-points-per-thread kernels
+// (512 threads) rather than the 32-points ones (1024 threads). Measured on
+// MI355X, forward: wide is faster for every split grid with at least 4096
+// columns (8192 x 8192: 0.552 against 0.594 ms; 8192 x 4096, 16384 x 4096,
+// 16384 x 8192: 8-12 %) and slower for 16384 x 2048 (0.292 against 0.279 ms
+// cold). FFT2D_SPLIT_COLUMN=narrow|wide overrides (default auto).
+bool use_wide_columns(int64_t cols) {
+  const char* env = std::getenv("FFT2D_SPLIT_COLUMN");
+  if (env && std::strcmp(env, "narrow") == 0) return false;
+  if (env && std::strcmp(env, "wide") == 0) return true;
+  return cols >= 4096;
+}
+
 // Same FFT length and radix sequence (hence the same twiddle table).
 bool same_schedule(const PassKernel& a, const PassKernel& b) {
   if (a.L != b.L || a.npass != b.npass) return false;
@@ -359,7 +372,7 @@ fft2d_status fft2d_plan(fft2d_plan_t* out, int64_t batch, int64_t rows, int64_t 
   p->m2 = rows / p->m1;
   if (p->m1 > 1) {
     p->row_k = find_combine_kernel((int)cols, (int)p->m1);
-    p->col_k = find_split_column_kernel((int)p->m2);
+    p->col_k = find_split_column_kernel((int)p->m2, use_wide_columns(cols));
     if (!p->col_k) p->col_k = find_pass_kernel((int)p->m2, true);
   } else {
     if (cols > 1) p->row_k = find_pass_kernel((int)cols, false);

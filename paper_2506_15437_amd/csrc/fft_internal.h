@@ -67,8 +67,9 @@ struct GridKernel {
 const PassKernel* find_pass_kernel(int L, bool colmode);
 // Row pass with an M1-point combine across M1 rows of length L (nullptr if none).
 const PassKernel* find_combine_kernel(int L, int m1);
-// Column pass for the length-M2 columns of a split transform.
-const PassKernel* find_split_column_kernel(int L);
+// Column pass for the length-M2 columns of a split transform; `wide` prefers
+// the 64-points-per-thread variant where there is one (large grids).
+const PassKernel* find_split_column_kernel(int L, bool wide = false);
 // Whole-grid kernel for rows x cols grids (nullptr if none).
 const GridKernel* find_grid_kernel(int rows, int cols);
 // All compiled variants for a length (for the autotuner); returns the count.

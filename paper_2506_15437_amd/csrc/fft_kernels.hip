@@ -34,8 +34,13 @@ const PassKernel* find_combine_kernel(int L, int m1) {
   return nullptr;
 }
 
-const PassKernel* find_split_column_kernel(int L) {
+const PassKernel* find_split_column_kernel(int L, bool wide) {
   int n = 0;
+  if (wide) {
+    const PassKernel* tab = split_col_wide_kernel_table(&n);
+    for (int i = 0; i < n; ++i)
+      if (tab[i].L == L) return &tab[i];
+  }
   const PassKernel* tab = split_col_kernel_table(&n);
   for (int i = 0; i < n; ++i)
     if (tab[i].L == L) return &tab[i];

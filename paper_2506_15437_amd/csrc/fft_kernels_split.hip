@@ -32,6 +32,14 @@ const PassKernel kCombineKernels[] = {
 const PassKernel kSplitColKernels[] = {
     describe<S512>(), describe<S1024>(), describe<S2048>(), describe<S4096>(),
 };
+// Column passes with 64 points per thread (512 threads) for split transforms
+// whose data come from HBM rather than the MALL (large grids): more loads in
+// flight per thread, fewer waves.
+using S2048W = Cfg<2048, 64, 16, 2, true, 16, 16, 8>;
+using S4096W = Cfg<4096, 64, 8, 4, true, 16, 16, 16>;
+const PassKernel kSplitColWideKernels[] = {
+    describe<S2048W>(), describe<S4096W>(),
+};
 
 }  // namespace
 
@@ -43,6 +51,11 @@ const PassKernel* combine_kernel_table(int* count) {
 const PassKernel* split_col_kernel_table(int* count) {
   *count = (int)(sizeof(kSplitColKernels) / sizeof(kSplitColKernels[0]));
   return kSplitColKernels;
+}
+
+const PassKernel* split_col_wide_kernel_table(int* count) {
+  *count = (int)(sizeof(kSplitColWideKernels) / sizeof(kSplitColWideKernels[0]));
+  return kSplitColWideKernels;
 }
 
 }  // namespace fft2d

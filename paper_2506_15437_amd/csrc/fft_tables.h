@@ -9,6 +9,7 @@ const PassKernel* row_kernel_table(int* count);
 const PassKernel* col_kernel_table(int* count);
 const PassKernel* combine_kernel_table(int* count);
 const PassKernel* split_col_kernel_table(int* count);
+const PassKernel* split_col_wide_kernel_table(int* count);
 const GridKernel* grid_kernel_table(int* count);
 
 }  // namespace fft2d

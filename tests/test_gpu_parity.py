@@ -267,7 +267,38 @@ def test_auto_split_choice(F):
         assert "split=4 " in p.describe(), p.describe()
         assert "split=1 " in q.describe(), q.describe()
         assert "split=4 " in r.describe(), r.describe()
+        assert " E=64 " in r.describe().split("col[")[1], r.describe()  # 8192 columns: wide column pass
     finally:
         p.close()
         q.close()
         r.close()
+
+
+@pytest.mark.parametrize("shape,mode,col_e", [((8192, 4096), "auto", 64), ((8192, 4096), "narrow", 32),
+                                              ((16384, 4096), "auto", 64), ((16384, 4096), "narrow", 32),
+                                              ((16384, 2048), "wide", 64)], ids=lambda v: str(v))
+def test_split_column_kernel_width(F, shape, mode, col_e, monkeypatch):
+    """Split plans' column passes of length 2048 and 4096 with 64 points per
+    thread (the default for at least 4096 columns) and with 32, against the
+    oracle (forward and inverse)."""
+    say("case split column width %dx%d %s" % (shape + (mode,)))
+    if mode == "auto":
+        monkeypatch.delenv("FFT2D_SPLIT_COLUMN", raising=False)
+    else:
+        monkeypatch.setenv("FFT2D_SPLIT_COLUMN", mode)
+    plan = F.Plan(1, *shape)
+    try:
+        desc = plan.describe()
+        say(desc)
+        col = desc[desc.index("col["):]
+        assert ("E=%d " % col_e) in col, desc
+        x = synth.complex_grid(40 + shape[1] // 1024, shape)
+        xd = dev(x)
+        err = rel_l2(host(plan(xd, F.FORWARD)), oracle.fft2_forward(x))
+        say("split column E=%d %dx%d fwd rel_l2=%.3e" % ((col_e,) + shape + (err,)))
+        assert err <= TOL
+        err = rel_l2(host(plan(xd, F.INVERSE)), oracle.ifft2(x))
+        say("split column E=%d %dx%d inv rel_l2=%.3e" % ((col_e,) + shape + (err,)))
+        assert err <= TOL
+    finally:
+        plan.close()
