@@ -87,9 +87,10 @@ typedef struct fft2d_plan_s* fft2d_plan_t;
  * angle and rounded once; the paper precomputes its twiddles at start-up,
  * Section 4) in device memory on the current HIP device, and chooses the radix
  * schedule and tile shape for each pass. Grids of at least 2^22 points with
- * 1024 <= cols <= 8192 use a split column transform (rows = M1 * M2: the row
- * pass also applies the first M1-point stage of the column FFT, the column pass
- * the remaining length-M2 stage), which needs a plan-owned work buffer of
+ * 1024 <= cols <= 8192, and grids of 16384 columns with at least 4096 rows,
+ * use a split column transform (rows = M1 * M2: the row pass also applies the
+ * first M1-point stage of the column FFT, the column pass the remaining
+ * length-M2 stage), which needs a plan-owned work buffer of
  * batch*rows*cols complex64 points; the environment variable FFT2D_SPLIT
  * (off | auto | M1) overrides the choice at plan time, FFT2D_SPLIT_COLUMN
  * (narrow | auto | wide) the column kernel's points per thread (32 | 64; auto

@@ -59,7 +59,12 @@ int64_t choose_split(int64_t rows, int64_t cols) {
     const int64_t m1 = std::atoll(env);
     return usable(m1) ? m1 : 1;
   }
-  if (rows * cols < (int64_t(1) << 22) || cols > 8192) return 1;
+  if (rows * cols < (int64_t(1) << 22)) return 1;
+  // cols = 16384: the unsplit column pass runs tiles of 2-4 columns; M1 = 2
+  // (32768 points per workgroup) measured faster from 4096 rows on (8192 x
+  // 16384: 1.28 against 1.47 ms) and slower below (2048 x 16384: 0.31 against
+  // 0.25 ms).
+  if (cols == 16384) return rows >= 4096 && usable(2) ? 2 : 1;
   // M1 rows of the combine fill one workgroup (16384 points; 32768 for
   // cols = 8192, where M1 = 2 would leave 4096-long, 64-byte-wide columns).
   const int64_t m1 = cols == 8192 ? 4 : 16384 / cols;

@@ -14,6 +14,7 @@ namespace {
 // one 256 KiB variant of 1024 threads for L = 8192).
 using RC8192x2 = Cfg<8192, 32, 2, 2, false, 16, 16, 32>;
 using RC8192x4 = Cfg<8192, 32, 4, 2, false, 16, 16, 32>;
+using RC16384x2 = Cfg<16384, 32, 2, 2, false, 16, 16, 16, 4>;
 using RC4096x4 = Cfg<4096, 32, 4, 2, false, 16, 16, 16>;
 using RC2048x8 = Cfg<2048, 32, 8, 2, false, 16, 16, 8>;
 using RC1024x16 = Cfg<1024, 32, 16, 2, false, 16, 16, 4>;
@@ -25,7 +26,8 @@ using S2048 = Cfg<2048, 32, 16, 2, true, 16, 16, 8>;
 using S4096 = Cfg<4096, 32, 8, 2, true, 16, 16, 16>;
 
 const PassKernel kCombineKernels[] = {
-    describe<RC8192x2, true, 4>(), describe<RC8192x4, true, 1>(), describe<RC4096x4, true, 4>(),
+    describe<RC8192x2, true, 4>(), describe<RC8192x4, true, 1>(), describe<RC16384x2, true, 1>(),
+    describe<RC4096x4, true, 4>(),
     describe<RC2048x8, true, 4>(),
     describe<RC1024x16, true, 4>(),
 };
@@ -37,8 +39,9 @@ const PassKernel kSplitColKernels[] = {
 // flight per thread, fewer waves.
 using S2048W = Cfg<2048, 64, 16, 2, true, 16, 16, 8>;
 using S4096W = Cfg<4096, 64, 8, 4, true, 16, 16, 16>;
+using S8192W = Cfg<8192, 64, 4, 2, true, 16, 16, 32>;
 const PassKernel kSplitColWideKernels[] = {
-    describe<S2048W>(), describe<S4096W>(),
+    describe<S2048W>(), describe<S4096W>(), describe<S8192W>(),
 };
 
 }  // namespace

@@ -224,7 +224,7 @@ def test_abi_errors_on_device_pointers(F):
 SPLIT_CASES = [(1, (32, 1024), 16), (2, (64, 1024), 16), (1, (256, 2048), 8), (3, (64, 2048), 8),
                (1, (512, 4096), 4), (2, (128, 4096), 4), (1, (64, 8192), 2), (1, (64, 8192), 4),
                (2, (32, 8192), 4), (1, (2048, 1024), 16),
-               (1, (8192, 2048), 8)]
+               (1, (8192, 2048), 8), (1, (64, 16384), 2), (2, (32, 16384), 2)]
 
 
 @pytest.mark.parametrize("batch,shape,m1", SPLIT_CASES, ids=lambda v: str(v))
@@ -263,7 +263,11 @@ def test_auto_split_choice(F):
     p = F.Plan(1, 4096, 4096)
     q = F.Plan(1, 64, 64)
     r = F.Plan(1, 8192, 8192)
+    u = F.Plan(1, 4096, 16384)
+    v = F.Plan(1, 2048, 16384)
     try:
+        assert "split=2 " in u.describe(), u.describe()
+        assert "split=1 " in v.describe(), v.describe()
         assert "split=4 " in p.describe(), p.describe()
         assert "split=1 " in q.describe(), q.describe()
         assert "split=4 " in r.describe(), r.describe()
@@ -272,11 +276,14 @@ def test_auto_split_choice(F):
         p.close()
         q.close()
         r.close()
+        u.close()
+        v.close()
 
 
 @pytest.mark.parametrize("shape,mode,col_e", [((8192, 4096), "auto", 64), ((8192, 4096), "narrow", 32),
                                               ((16384, 4096), "auto", 64), ((16384, 4096), "narrow", 32),
-                                              ((16384, 2048), "wide", 64)], ids=lambda v: str(v))
+                                              ((16384, 2048), "wide", 64), ((4096, 16384), "auto", 64)],
+                         ids=lambda v: str(v))
 def test_split_column_kernel_width(F, shape, mode, col_e, monkeypatch):
     """Split plans' column passes of length 2048 and 4096 with 64 points per
     thread (the default for at least 4096 columns) and with 32, against the
