@@ -48,7 +48,7 @@ enum PlanKind { kUniform = 1, kBatched = 2 };
 // (1 = plain two-pass transform). Large grids split so that the row pass holds
 // M1 rows of 128 KiB in total and the column pass works on columns of
 // rows / M1 points in 16-column tiles. FFT2D_SPLIT=off|auto|<M1> overrides.
-int64_t choose_split(int64_t rows, int64_t cols) {
+int64_t choose_split(int64_t batch, int64_t rows, int64_t cols) {
   auto usable = [&](int64_t m1) {
     return m1 > 1 && rows % m1 == 0 && rows / m1 >= 2 && fft2d::find_combine_kernel((int)cols, (int)m1) &&
            (fft2d::find_split_column_kernel((int)(rows / m1)) || fft2d::find_pass_kernel((int)(rows / m1), true));
@@ -60,6 +60,15 @@ int64_t choose_split(int64_t rows, int64_t cols) {
     return usable(m1) ? m1 : 1;
   }
   if (rows * cols < (int64_t(1) << 22)) return 1;
+  // A plan of 192-256 MiB in total with columns of at most 4096 points: the
+  // split's work buffer is a third buffer of that size beside input and
+  // output, which the 256 MB MALL no longer absorbs, and the unsplit column
+  // pass (tiles of 8-16 columns) measured faster (8 x 2048^2: 0.217 against
+  // 0.232 ms; 2 x 4096^2: 0.223 against 0.257 ms; 4096 x 8192: 0.245 against
+  // 0.287 ms). Outside that window (e.g. 160 or 288 MiB, or one 4096^2 grid)
+  // the split was faster.
+  const int64_t bytes = batch * rows * cols * (int64_t)sizeof(float2);
+  if (rows <= 4096 && bytes >= (int64_t(192) << 20) && bytes <= (int64_t(256) << 20)) return 1;
   // cols = 16384: the unsplit column pass runs tiles of 2-4 columns; M1 = 2
   // (32768 points per workgroup) measured faster from 4096 rows on (8192 x
   // 16384: 1.28 against 1.47 ms) and slower below (2048 x 16384: 0.31 against
@@ -373,7 +382,7 @@ fft2d_status fft2d_plan(fft2d_plan_t* out, int64_t batch, int64_t rows, int64_t 
     delete p;
     return hip_fail(e, "hipGetDevice");
   }
-  p->m1 = choose_split(rows, cols);
+  p->m1 = choose_split(batch, rows, cols);
   p->m2 = rows / p->m1;
   if (p->m1 > 1) {
     p->row_k = find_combine_kernel((int)cols, (int)p->m1);

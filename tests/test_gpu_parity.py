@@ -265,7 +265,11 @@ def test_auto_split_choice(F):
     r = F.Plan(1, 8192, 8192)
     u = F.Plan(1, 4096, 16384)
     v = F.Plan(1, 2048, 16384)
+    w = F.Plan(8, 2048, 2048)  # 256 MiB with 2048-point columns: unsplit
+    z = F.Plan(4, 2048, 2048)
     try:
+        assert "split=1 " in w.describe(), w.describe()
+        assert "split=8 " in z.describe(), z.describe()
         assert "split=2 " in u.describe(), u.describe()
         assert "split=1 " in v.describe(), v.describe()
         assert "split=4 " in p.describe(), p.describe()
@@ -278,6 +282,8 @@ def test_auto_split_choice(F):
         r.close()
         u.close()
         v.close()
+        w.close()
+        z.close()
 
 
 @pytest.mark.parametrize("shape,mode,col_e", [((8192, 4096), "auto", 64), ((8192, 4096), "narrow", 32),
