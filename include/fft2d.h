@@ -36,11 +36,12 @@
  * points, see fft2d_plan), outputs are untouched, and fft2d_last_error() gives
  * a thread-local detail string.
  *
- * Thread safety: a plain uniform plan is read-only during execution and may be
- * used from several host threads and streams at once. A split plan (large
- * grids; see fft2d_plan) and a batched plan own mutable device memory (work
- * buffer; work counters and descriptor table): use each from one stream at a
- * time, and a batched plan from one host thread at a time.
+ * Thread safety: a uniform plan is read-only during out-of-place execution and
+ * may be used from several host threads and streams at once. In-place calls of
+ * a split plan (large grids; see fft2d_plan) and every call of a batched plan
+ * use mutable plan memory (work buffer; work counters and descriptor table):
+ * such calls on one plan must not overlap (one stream at a time), and a batched
+ * plan is used from one host thread at a time.
  */
 #ifndef FFT2D_H
 #define FFT2D_H
@@ -87,14 +88,15 @@ typedef struct fft2d_plan_s* fft2d_plan_t;
  * angle and rounded once; the paper precomputes its twiddles at start-up,
  * Section 4) in device memory on the current HIP device, and chooses the radix
  * schedule and tile shape for each pass. Grids of at least 2^22 points with
- * 1024 <= cols <= 8192, and grids of 16384 columns with at least 4096 rows,
+ * 1024 <= cols <= 8192, and grids of 16384 columns with at least 2048 rows,
  * use a split column transform (rows = M1 * M2: the row pass also applies the
  * first M1-point stage of the column FFT, the column pass the remaining
- * length-M2 stage), which needs a plan-owned work buffer of
- * batch*rows*cols complex64 points; the environment variable FFT2D_SPLIT
+ * length-M2 stage). An out-of-place call keeps the intermediate in `out`; an
+ * in-place call needs the plan-owned work buffer of batch*rows*cols complex64
+ * points, allocated here. The environment variable FFT2D_SPLIT
  * (off | auto | M1) overrides the choice at plan time, FFT2D_SPLIT_COLUMN
  * (narrow | auto | wide) the column kernel's points per thread (32 | 64; auto
- * takes 64 where there is such a kernel and cols >= 4096). Grids of 32 x 32,
+ * takes 64 where there is such a kernel). Grids of 32 x 32,
  * 32 x 64, 64 x 32, 64 x 64, 32 x 128, 128 x 32, 64 x 128, 128 x 64, 128 x 128,
  * 32 x 256, 256 x 32, 64 x 256 and 256 x 64 run both passes in one whole-grid
  * launch (one workgroup per grid, every point read and written once) when the
@@ -177,7 +179,8 @@ fft2d_status fft2d_backward(fft2d_plan_t plan, const void* grad_out, void* grad_
  * every row; for split plans also the first, M1-point stage of the column
  * transform), pass 1 the column pass. Pass 0 reads `in` and writes the
  * intermediate result; pass 1 reads the intermediate and writes `out`. The
- * intermediate is the plan's work buffer for split plans and `out` otherwise,
+ * intermediate is `out`, except for in-place calls (in == out) of split
+ * plans, where it is the plan's work buffer,
  * so pass 0 then pass 1 with the same arguments is exactly fft2d_exec (for a
  * plan that runs the whole-grid kernel: the same transform in two launches,
  * equal to it up to rounding). The

@@ -48,7 +48,7 @@ enum PlanKind { kUniform = 1, kBatched = 2 };
 // (1 = plain two-pass transform). Large grids split so that the row pass holds
 // M1 rows of 128 KiB in total and the column pass works on columns of
 // rows / M1 points in 16-column tiles. FFT2D_SPLIT=off|auto|<M1> overrides.
-int64_t choose_split(int64_t batch, int64_t rows, int64_t cols) {
+int64_t choose_split(int64_t rows, int64_t cols) {
   auto usable = [&](int64_t m1) {
     return m1 > 1 && rows % m1 == 0 && rows / m1 >= 2 && fft2d::find_combine_kernel((int)cols, (int)m1) &&
            (fft2d::find_split_column_kernel((int)(rows / m1)) || fft2d::find_pass_kernel((int)(rows / m1), true));
@@ -60,20 +60,11 @@ int64_t choose_split(int64_t batch, int64_t rows, int64_t cols) {
     return usable(m1) ? m1 : 1;
   }
   if (rows * cols < (int64_t(1) << 22)) return 1;
-  // A plan of 192-256 MiB in total with columns of at most 4096 points: the
-  // split's work buffer is a third buffer of that size beside input and
-  // output, which the 256 MB MALL no longer absorbs, and the unsplit column
-  // pass (tiles of 8-16 columns) measured faster (8 x 2048^2: 0.217 against
-  // 0.232 ms; 2 x 4096^2: 0.223 against 0.257 ms; 4096 x 8192: 0.245 against
-  // 0.287 ms). Outside that window (e.g. 160 or 288 MiB, or one 4096^2 grid)
-  // the split was faster.
-  const int64_t bytes = batch * rows * cols * (int64_t)sizeof(float2);
-  if (rows <= 4096 && bytes >= (int64_t(192) << 20) && bytes <= (int64_t(256) << 20)) return 1;
   // cols = 16384: the unsplit column pass runs tiles of 2-4 columns; M1 = 2
-  // (32768 points per workgroup) measured faster from 4096 rows on (8192 x
-  // 16384: 1.28 against 1.47 ms) and slower below (2048 x 16384: 0.31 against
-  // 0.25 ms).
-  if (cols == 16384) return rows >= 4096 && usable(2) ? 2 : 1;
+  // (32768 points per workgroup) measured faster from 2048 rows on (8192 x
+  // 16384: 1.21 against 1.29 ms; 2048 x 16384: 0.238 against 0.250 ms) and
+  // not below (1024 x 16384: 0.119 against 0.118 ms).
+  if (cols == 16384) return rows >= 2048 && usable(2) ? 2 : 1;
   // M1 rows of the combine fill one workgroup (16384 points; 32768 for
   // cols = 8192, where M1 = 2 would leave 4096-long, 64-byte-wide columns).
   const int64_t m1 = cols == 8192 ? 4 : 16384 / cols;
@@ -95,16 +86,14 @@ bool use_grid_kernel(int64_t batch, int64_t points) {
 }
 
 // Whether a split plan's column pass uses the 64-points-per-thread kernels
-// (512 threads) rather than the 32-points ones (1024 threads). Measured on
-// MI355X, forward: wide is faster for every split grid with at least 4096
-// columns (8192 x 8192: 0.552 against 0.594 ms; 8192 x 4096, 16384 x 4096,
-// 16384 x 8192: 8-12 %) and slower for 16384 x 2048 (0.292 against 0.279 ms
-// cold). FFT2D_SPLIT_COLUMN=narrow|wide overrides (default auto).
-bool use_wide_columns(int64_t cols) {
+// (512 threads) where there is one (lengths 2048, 4096, 8192) rather than the
+// 32-points ones (1024 threads). Measured on MI355X, forward, faster for every
+// split shape tried (8192 x 8192: 0.545 against 0.576 ms; 16384 x 4096: 0.572
+// against 0.617; 2 x 16384 x 2048: 0.492 against 0.536; 16384 x 2048: 0.234
+// against 0.240). FFT2D_SPLIT_COLUMN=narrow|wide overrides (default auto).
+bool use_wide_columns() {
   const char* env = std::getenv("FFT2D_SPLIT_COLUMN");
-  if (env && std::strcmp(env, "narrow") == 0) return false;
-  if (env && std::strcmp(env, "wide") == 0) return true;
-  return cols >= 4096;
+  return !(env && std::strcmp(env, "narrow") == 0);
 }
 
 // Same FFT length and radix sequence (hence the same twiddle table).
@@ -123,7 +112,8 @@ struct fft2d_plan_s {
   int64_t batch = 0, rows = 0, cols = 0;
   // Plain transform (m1 == 1): row pass in -> out, column pass out -> out.
   // Split transform (m1 > 1, rows = m1 * m2): row pass with an m1-point
-  // combine in -> work, then a column pass of length m2 work -> out.
+  // combine in -> out, then a column pass of length m2 out -> out; in-place
+  // calls go through the work buffer (in -> work -> out).
   int64_t m1 = 1, m2 = 0;
   const PassKernel* row_k = nullptr;  // length-cols FFT along rows (null if cols == 1)
   const PassKernel* col_k = nullptr;  // length-rows (or m2) FFT down columns (null if rows == 1)
@@ -226,10 +216,14 @@ fft2d_status run_grids(const fft2d_plan_s* p, int64_t nb, const float2* in, floa
     return e == hipSuccess ? FFT2D_OK : hip_fail(e, "whole-grid kernel launch");
   }
   if (p->m1 > 1) {
+    // The intermediate grid: `out` itself (the column pass then runs in place)
+    // unless the call is in place, where the row pass must not overwrite rows
+    // that other workgroups still read: then the plan's work buffer.
+    float2* mid = (static_cast<const void*>(in) == static_cast<const void*>(out)) ? work : out;
     if (only_pass != 1) {
       PassArgs a{};
       a.in = in;
-      a.out = work;
+      a.out = mid;
       a.tw = p->tw_row;
       a.tw_count = (int64_t)twiddle_count(*p->row_k);
       a.total = npts;
@@ -245,7 +239,7 @@ fft2d_status run_grids(const fft2d_plan_s* p, int64_t nb, const float2* in, floa
     }
     if (only_pass != 0) {
       PassArgs a{};
-      a.in = work;
+      a.in = mid;
       a.out = out;
       a.tw = p->tw_col;
       a.tw_count = (int64_t)twiddle_count(*p->col_k);
@@ -382,11 +376,11 @@ fft2d_status fft2d_plan(fft2d_plan_t* out, int64_t batch, int64_t rows, int64_t 
     delete p;
     return hip_fail(e, "hipGetDevice");
   }
-  p->m1 = choose_split(batch, rows, cols);
+  p->m1 = choose_split(rows, cols);
   p->m2 = rows / p->m1;
   if (p->m1 > 1) {
     p->row_k = find_combine_kernel((int)cols, (int)p->m1);
-    p->col_k = find_split_column_kernel((int)p->m2, use_wide_columns(cols));
+    p->col_k = find_split_column_kernel((int)p->m2, use_wide_columns());
     if (!p->col_k) p->col_k = find_pass_kernel((int)p->m2, true);
   } else {
     if (cols > 1) p->row_k = find_pass_kernel((int)cols, false);

@@ -13,15 +13,17 @@ constexpr int kMaxPasses = 6;
 // Arguments of one pass launch. A pass applies a length-L FFT to `nvec`
 // vectors. Row mode: vector v is the L contiguous points starting at v*L.
 // Column mode: vector v = g*ncols + col is column `col` of grid g, its element
-// e at g*L*ncols + e*ncols + col (stride ncols points).
+// e at g*L*ncols + e*ncols + col (stride ncols points; with m1 > 1, vector
+// v = (g*m1 + k1)*ncols + col has element e at row k1 + m1*e of grid g).
 //
 // Split column transform (M = M1 * M2). A row pass with combine handles, per
 // workgroup, the M1 rows M2*m1 + m2 (m1 < M1) of one grid: it transforms each
 // row, applies an M1-point DFT across them (m1 -> k1), multiplies output k1 by
-// W_M^(m2 k1) and stores it to row M2*k1 + m2. A column pass with m1 = M1 then
-// transforms length-M2 columns of the row block [M2*k1, M2*k1 + M2) and
-// stores element k2 to row k1 + M1*k2. Together they are the length-M column
-// DFT (four-step factorisation); m1 = 1 is the plain column pass.
+// W_M^(m2 k1) and stores it to row M1*m2 + k1. A column pass with m1 = M1 then
+// transforms, for each k1, the length-M2 column of rows k1 + M1*m2 (m2 < M2)
+// and stores element k2 to row k1 + M1*k2: the same rows, so it can run in
+// place. Together they are the length-M column DFT (four-step
+// factorisation); m1 = 1 is the plain column pass.
 struct PassArgs {
   const float2* in;
   float2* out;

@@ -386,29 +386,22 @@ __device__ __forceinline__ void fft_tile(const PassArgs& a, int w, float2* lds, 
   int64_t base_in, base_out, es_in, es_out;
   uint32_t lane_in, lane_out;  // point offsets of this lane's vector from the tile bases
   if constexpr (K::COL) {
-    // vector v = (grid g, row block k1, column col); element e of the block
-    // is row M2*k1 + e on input and row k1 + M1*e on output (M2 = L).
+    // vector v = (grid g, residue k1, column col); element e is row
+    // k1 + M1*e of grid g on input and on output (M1 = a.m1; plain column
+    // pass: M1 = 1), so a tile reads and writes the same points.
     const int64_t per_g = a.m1 * a.ncols;
-    auto start = [&](int64_t v, int64_t& in_pt, int64_t& out_pt) {
+    auto start = [&](int64_t v) {
       const int64_t g = v / per_g;
-      const int64_t rem = v - g * per_g;
-      const int64_t k1 = rem / a.ncols;
-      const int64_t col = rem - k1 * a.ncols;
-      const int64_t gbase = g * (int64_t)K::L * per_g;
-      in_pt = gbase + k1 * (int64_t)K::L * a.ncols + col;
-      out_pt = gbase + k1 * a.ncols + col;
+      const int64_t rem = v - g * per_g;  // = k1 * ncols + col
+      return g * (int64_t)K::L * per_g + rem;
     };
-    start(v0, base_in, base_out);
-    if (a.ncols >= K::C) {  // the tile's columns share one grid and row block
+    base_in = base_out = start(v0);
+    if (a.ncols >= K::C) {  // the tile's columns share one grid and residue
       lane_in = lane_out = (uint32_t)c;
     } else {
-      int64_t li, lo;
-      start(v0 + c, li, lo);
-      lane_in = (uint32_t)(li - base_in);
-      lane_out = (uint32_t)(lo - base_out);
+      lane_in = lane_out = (uint32_t)(start(v0 + c) - base_in);
     }
-    es_in = a.ncols;
-    es_out = per_g;
+    es_in = es_out = per_g;
   } else {
     base_in = base_out = v0 * K::L;
     lane_in = lane_out = (uint32_t)(c * K::L);
@@ -451,7 +444,8 @@ __global__ __launch_bounds__(K::THREADS) __attribute__((amdgpu_waves_per_eu(WPE)
 // Row pass with combine (first half of a split column transform, see
 // PassArgs): tile w = (grid g, m2) transforms the M1 = C rows M2*m1 + m2,
 // then for every column position an M1-point DFT across those rows and the
-// twiddle W_M^(m2 k1), stored to row M2*k1 + m2. The rows' transformed points
+// twiddle W_M^(m2 k1), stored to row M1*m2 + k1 (the tile's output is the M1
+// consecutive rows starting at row M1*m2). The rows' transformed points
 // are exchanged through LDS in Q rounds of L/Q positions; in each round every
 // thread owns L/(Q*THREADS) positions and all M1 rows of each. Only
 // io.conj_in is honoured (the output is an intermediate, never final).
@@ -468,10 +462,12 @@ __device__ __forceinline__ void rowc_tile(const PassArgs& a, int64_t w, float2* 
   const int64_t g = w / a.m2;
   const int64_t m2 = w - g * a.m2;
   const int64_t gbase = g * a.m2 * M1 * K::L;
-  // rows M2*c + m2 of grid g: the tile base is row m2, lane rows c*M2 further
+  // input rows M2*c + m2 of grid g: the tile base is row m2, lane rows c*M2
+  // further; output rows M1*m2 + k1
   const int64_t base = gbase + m2 * K::L;
+  const int64_t obase = gbase + m2 * M1 * K::L;
   const Buf src(a.in + base, span_bytes(a.total, base));
-  const Buf dst(a.out + base, span_bytes(a.total, base));
+  const Buf dst(a.out + obase, span_bytes(a.total, obase));
   const Buf tw(a.tw, (uint32_t)a.tw_count * 8u);
   const uint32_t row_bytes = (uint32_t)(a.m2 * K::L) * 8u;  // from row m2 + M2*k to row m2 + M2*(k+1)
   const uint32_t voff_in = (uint32_t)c * row_bytes + (uint32_t)tt * 8u;
@@ -510,7 +506,7 @@ __device__ __forceinline__ void rowc_tile(const PassArgs& a, int64_t w, float2* 
       const uint32_t voff = (uint32_t)(h * NQ + K::THREADS * i + t) * 8u;
       static_for<0, M1>([&](auto Kk) {
         constexpr int k1 = decltype(Kk)::value;
-        dst.store((k1 == 0) ? x[0] : cmul(x[k1], wk[k1]), voff, (uint32_t)k1 * row_bytes);
+        dst.store((k1 == 0) ? x[0] : cmul(x[k1], wk[k1]), voff, (uint32_t)(k1 * K::L) * 8u);
       });
     });
     __syncthreads();

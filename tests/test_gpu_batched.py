@@ -72,8 +72,8 @@ SPLIT_EXPECTED = 8  # the first eight are split
 
 @pytest.mark.parametrize("split", ["auto", "off"])
 def test_batched_split_transforms(F, split, monkeypatch):
-    """Forward, inverse and in place for tall grids in one plan, split (row pass
-    with an M1-point combine into a plan work buffer, columns of M / M1) or not."""
+    """Forward, inverse, in place and half in place for tall grids in one plan,
+    split (row pass with an M1-point combine, columns of M / M1) or not."""
     import torch
     monkeypatch.setenv("FFT2D_TUNE", "off")
     monkeypatch.setenv("FFT2D_BATCH_SPLIT", split)
@@ -97,6 +97,13 @@ def test_batched_split_transforms(F, split, monkeypatch):
         plan(inplace, F.FORWARD, inplace)
         torch.cuda.synchronize()
         for u, v in zip(ys, inplace):
+            assert torch.equal(u, v)
+        # every other transform in place (per-transform pointers)
+        mixed_in = [t.clone() for t in ins]
+        mixed_out = [t if k % 2 == 0 else torch.empty_like(t) for k, t in enumerate(mixed_in)]
+        plan(mixed_in, F.FORWARD, mixed_out)
+        torch.cuda.synchronize()
+        for u, v in zip(ys, mixed_out):
             assert torch.equal(u, v)
     finally:
         plan.close()
