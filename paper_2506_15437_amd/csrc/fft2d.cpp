@@ -96,6 +96,17 @@ bool use_wide_columns() {
   return !(env && std::strcmp(env, "narrow") == 0);
 }
 
+// Whether a plain column pass over `vectors` columns, whose default kernel
+// takes `c` columns per tile, uses the narrower-tile kernel: when the default
+// would leave fewer tiles than the GPU has CUs. FFT2D_FEW_TILES=off|on
+// overrides (default auto).
+bool use_few_tiles_kernel(int64_t vectors, int c) {
+  const char* env = std::getenv("FFT2D_FEW_TILES");
+  if (env && std::strcmp(env, "off") == 0) return false;
+  if (env && std::strcmp(env, "on") == 0) return true;
+  return vectors / c < 256;
+}
+
 // Same FFT length and radix sequence (hence the same twiddle table).
 bool same_schedule(const PassKernel& a, const PassKernel& b) {
   if (a.L != b.L || a.npass != b.npass) return false;
@@ -385,6 +396,9 @@ fft2d_status fft2d_plan(fft2d_plan_t* out, int64_t batch, int64_t rows, int64_t 
   } else {
     if (cols > 1) p->row_k = find_pass_kernel((int)cols, false);
     if (rows > 1) p->col_k = find_pass_kernel((int)rows, true);
+    if (p->col_k && use_few_tiles_kernel(batch * cols, p->col_k->C)) {
+      if (const PassKernel* f = find_few_tiles_column_kernel((int)rows)) p->col_k = f;
+    }
     const GridKernel* g = find_grid_kernel((int)rows, (int)cols);
     if (g && p->row_k && p->col_k && same_schedule(g->row, *p->row_k) && same_schedule(g->col, *p->col_k) &&
         use_grid_kernel(batch, rows * cols))

@@ -26,6 +26,14 @@ const PassKernel* find_pass_kernel(int L, bool colmode) {
   return nullptr;
 }
 
+const PassKernel* find_few_tiles_column_kernel(int L) {
+  int n = 0;
+  const PassKernel* tab = col_few_kernel_table(&n);
+  for (int i = 0; i < n; ++i)
+    if (tab[i].L == L) return &tab[i];
+  return nullptr;
+}
+
 const PassKernel* find_combine_kernel(int L, int m1) {
   int n = 0;
   const PassKernel* tab = combine_kernel_table(&n);

@@ -25,6 +25,15 @@ using C4096 = Cfg<4096, 32, 8, 2, true, 16, 16, 16>;
 using C8192 = Cfg<8192, 32, 4, 2, true, 16, 16, 32>;
 using C16384 = Cfg<16384, 32, 2, 2, true, 16, 16, 16, 4>;
 
+// Narrower tiles for column passes that would otherwise leave most CUs idle
+// (fewer tiles than CUs, e.g. one 1024 x 1024 grid: 64 tiles of 16 columns).
+using C512F = Cfg<512, 16, 8, 1, true, 16, 16, 2>;     // 256 threads, 8 columns
+using C1024F = Cfg<1024, 16, 4, 1, true, 16, 16, 4>;   // 256 threads, 4 columns
+using C2048F = Cfg<2048, 16, 4, 1, true, 16, 16, 8>;   // 512 threads, 4 columns
+const PassKernel kColFewKernels[] = {
+    describe<C512F>(), describe<C1024F>(), describe<C2048F>(),
+};
+
 const PassKernel kColKernels[] = {
     describe<C2>(),   describe<C4>(),   describe<C8>(),    describe<C16>(),   describe<C32>(),
     describe<C64>(),  describe<C128>(), describe<C256>(),  describe<C512>(),  describe<C1024>(),
@@ -32,6 +41,11 @@ const PassKernel kColKernels[] = {
 };
 
 }  // namespace
+
+const PassKernel* col_few_kernel_table(int* count) {
+  *count = (int)(sizeof(kColFewKernels) / sizeof(kColFewKernels[0]));
+  return kColFewKernels;
+}
 
 const PassKernel* col_kernel_table(int* count) {
   *count = (int)(sizeof(kColKernels) / sizeof(kColKernels[0]));

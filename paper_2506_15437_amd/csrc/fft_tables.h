@@ -7,6 +7,7 @@ namespace fft2d {
 
 const PassKernel* row_kernel_table(int* count);
 const PassKernel* col_kernel_table(int* count);
+const PassKernel* col_few_kernel_table(int* count);
 const PassKernel* combine_kernel_table(int* count);
 const PassKernel* split_col_kernel_table(int* count);
 const PassKernel* split_col_wide_kernel_table(int* count);

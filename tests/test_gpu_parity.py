@@ -312,3 +312,29 @@ def test_split_column_kernel_width(F, shape, mode, col_e, monkeypatch):
         assert err <= TOL
     finally:
         plan.close()
+
+
+@pytest.mark.parametrize("shape", [(1024, 1024), (512, 512), (2048, 1024)], ids=lambda s: "%dx%d" % s)
+@pytest.mark.parametrize("mode", ["auto", "off"])
+def test_few_tiles_column_kernel(F, shape, mode, monkeypatch):
+    """Column passes with fewer tiles than CUs use narrower tiles (4-8 columns)
+    by default; both kernels against the oracle."""
+    say("case few-tiles column kernel %dx%d %s" % (shape + (mode,)))
+    if mode == "auto":
+        monkeypatch.delenv("FFT2D_FEW_TILES", raising=False)
+    else:
+        monkeypatch.setenv("FFT2D_FEW_TILES", mode)
+    plan = F.Plan(1, *shape)
+    try:
+        desc = plan.describe()
+        col = desc[desc.index("col["):]
+        narrow = (" C=4 " in col) or (" C=8 " in col and shape[0] == 512)
+        assert narrow == (mode == "auto"), desc
+        x = synth.complex_grid(60 + shape[0] // 512, shape)
+        xd = dev(x)
+        err_f = rel_l2(host(plan(xd, F.FORWARD)), oracle.fft2_forward(x))
+        err_i = rel_l2(host(plan(xd, F.INVERSE)), oracle.ifft2(x))
+        say("few-tiles %s %dx%d fwd %.3e inv %.3e" % ((mode,) + shape + (err_f, err_i)))
+        assert err_f <= TOL and err_i <= TOL
+    finally:
+        plan.close()
