@@ -102,8 +102,8 @@ typedef struct fft2d_plan_s* fft2d_plan_t;
  * launch (one workgroup per grid, every point read and written once) when the
  * batch is large enough to fill the GPU (any batch for grids of up to 4096
  * points, at least 32 grids of 8192 points, 128 grids of 16384); FFT2D_GRID
- * (off | auto | on) overrides that choice. A plain column pass that would run
- * fewer tiles than the GPU has CUs uses narrower tiles (FFT2D_FEW_TILES
+ * (off | auto | on) overrides that choice. Plain passes that would run about
+ * one tile per CU or fewer use narrower tiles (FFT2D_FEW_TILES
  * off | auto | on). Batches of more than 2^31 points run
  * as several launches of whole grids (a HIP launch holds fewer than 2^32
  * work-items); if one of those launches fails, the earlier ones stay enqueued.

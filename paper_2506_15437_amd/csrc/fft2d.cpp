@@ -96,15 +96,17 @@ bool use_wide_columns() {
   return !(env && std::strcmp(env, "narrow") == 0);
 }
 
-// Whether a plain column pass over `vectors` columns, whose default kernel
-// takes `c` columns per tile, uses the narrower-tile kernel: when the default
-// would leave fewer tiles than the GPU has CUs. FFT2D_FEW_TILES=off|on
-// overrides (default auto).
-bool use_few_tiles_kernel(int64_t vectors, int c) {
+// Whether a plain pass over `vectors` rows or columns, whose default kernel
+// takes `c` of them per tile, uses the narrower-tile kernel: when the default
+// would give at most one tile per CU (rows; one 1024^2 grid has 256 row tiles
+// and gains) or fewer (columns; at 256 column tiles the narrow kernel measured
+// 1-3 % slower). FFT2D_FEW_TILES=off|on overrides (default auto).
+bool use_few_tiles_kernel(int64_t vectors, int c, bool colmode) {
   const char* env = std::getenv("FFT2D_FEW_TILES");
   if (env && std::strcmp(env, "off") == 0) return false;
   if (env && std::strcmp(env, "on") == 0) return true;
-  return vectors / c < 256;
+  const int64_t tiles = vectors / c;
+  return colmode ? tiles < 256 : tiles <= 256;
 }
 
 // Same FFT length and radix sequence (hence the same twiddle table).
@@ -396,8 +398,11 @@ fft2d_status fft2d_plan(fft2d_plan_t* out, int64_t batch, int64_t rows, int64_t 
   } else {
     if (cols > 1) p->row_k = find_pass_kernel((int)cols, false);
     if (rows > 1) p->col_k = find_pass_kernel((int)rows, true);
-    if (p->col_k && use_few_tiles_kernel(batch * cols, p->col_k->C)) {
-      if (const PassKernel* f = find_few_tiles_column_kernel((int)rows)) p->col_k = f;
+    if (p->row_k && use_few_tiles_kernel(batch * rows, p->row_k->C, false)) {
+      if (const PassKernel* f = find_few_tiles_kernel((int)cols, false)) p->row_k = f;
+    }
+    if (p->col_k && use_few_tiles_kernel(batch * cols, p->col_k->C, true)) {
+      if (const PassKernel* f = find_few_tiles_kernel((int)rows, true)) p->col_k = f;
     }
     const GridKernel* g = find_grid_kernel((int)rows, (int)cols);
     if (g && p->row_k && p->col_k && same_schedule(g->row, *p->row_k) && same_schedule(g->col, *p->col_k) &&

@@ -67,9 +67,9 @@ struct GridKernel {
 
 // Default kernel for a length L in [2, 16384] (power of two); nullptr otherwise.
 const PassKernel* find_pass_kernel(int L, bool colmode);
-// Column pass of length L with narrower tiles, for passes with few tiles
-// (nullptr if none).
-const PassKernel* find_few_tiles_column_kernel(int L);
+// Pass of length L with narrower tiles, for passes with few tiles (nullptr
+// if none).
+const PassKernel* find_few_tiles_kernel(int L, bool colmode);
 // Row pass with an M1-point combine across M1 rows of length L (nullptr if none).
 const PassKernel* find_combine_kernel(int L, int m1);
 // Column pass for the length-M2 columns of a split transform; `wide` prefers

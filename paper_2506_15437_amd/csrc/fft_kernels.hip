@@ -26,9 +26,9 @@ const PassKernel* find_pass_kernel(int L, bool colmode) {
   return nullptr;
 }
 
-const PassKernel* find_few_tiles_column_kernel(int L) {
+const PassKernel* find_few_tiles_kernel(int L, bool colmode) {
   int n = 0;
-  const PassKernel* tab = col_few_kernel_table(&n);
+  const PassKernel* tab = colmode ? col_few_kernel_table(&n) : row_few_kernel_table(&n);
   for (int i = 0; i < n; ++i)
     if (tab[i].L == L) return &tab[i];
   return nullptr;

@@ -25,6 +25,13 @@ using R4096 = Cfg<4096, 16, 1, 1, false, 16, 16, 16>;
 using R8192 = Cfg<8192, 32, 1, 1, false, 32, 16, 16>;
 using R16384 = Cfg<16384, 64, 1, 2, false, 16, 16, 16, 4>;  // 256 threads, two workgroups per CU
 
+// One row of 1024 per 64-thread workgroup, for row passes with few tiles
+// (e.g. one 1024 x 1024 grid: 256 tiles of 4 rows, or 1024 of one).
+using R1024F = Cfg<1024, 16, 1, 1, false, 16, 16, 4>;
+const PassKernel kRowFewKernels[] = {
+    describe<R1024F>(),
+};
+
 const PassKernel kRowKernels[] = {
     describe<R2>(),   describe<R4>(),   describe<R8>(),    describe<R16>(),   describe<R32>(),
     describe<R64>(),  describe<R128>(), describe<R256>(),  describe<R512>(),  describe<R1024>(),
@@ -32,6 +39,11 @@ const PassKernel kRowKernels[] = {
 };
 
 }  // namespace
+
+const PassKernel* row_few_kernel_table(int* count) {
+  *count = (int)(sizeof(kRowFewKernels) / sizeof(kRowFewKernels[0]));
+  return kRowFewKernels;
+}
 
 const PassKernel* row_kernel_table(int* count) {
   *count = (int)(sizeof(kRowKernels) / sizeof(kRowKernels[0]));

@@ -6,6 +6,7 @@
 namespace fft2d {
 
 const PassKernel* row_kernel_table(int* count);
+const PassKernel* row_few_kernel_table(int* count);
 const PassKernel* col_kernel_table(int* count);
 const PassKernel* col_few_kernel_table(int* count);
 const PassKernel* combine_kernel_table(int* count);

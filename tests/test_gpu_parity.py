@@ -317,8 +317,8 @@ def test_split_column_kernel_width(F, shape, mode, col_e, monkeypatch):
 @pytest.mark.parametrize("shape", [(1024, 1024), (512, 512), (2048, 1024)], ids=lambda s: "%dx%d" % s)
 @pytest.mark.parametrize("mode", ["auto", "off"])
 def test_few_tiles_column_kernel(F, shape, mode, monkeypatch):
-    """Column passes with fewer tiles than CUs use narrower tiles (4-8 columns)
-    by default; both kernels against the oracle."""
+    """Passes with few tiles use narrower tiles by default (4-8 columns; one
+    row of 1024); both kernels against the oracle."""
     say("case few-tiles column kernel %dx%d %s" % (shape + (mode,)))
     if mode == "auto":
         monkeypatch.delenv("FFT2D_FEW_TILES", raising=False)
@@ -330,6 +330,9 @@ def test_few_tiles_column_kernel(F, shape, mode, monkeypatch):
         col = desc[desc.index("col["):]
         narrow = (" C=4 " in col) or (" C=8 " in col and shape[0] == 512)
         assert narrow == (mode == "auto"), desc
+        if shape == (1024, 1024):  # 256 row tiles of 4 rows: one row per tile instead
+            row = desc[desc.index("row["):desc.index("col[")]
+            assert (" C=1 " in row) == (mode == "auto"), desc
         x = synth.complex_grid(60 + shape[0] // 512, shape)
         xd = dev(x)
         err_f = rel_l2(host(plan(xd, F.FORWARD)), oracle.fft2_forward(x))
