@@ -527,6 +527,15 @@ def main():
         result["backward_vs_plain"] = time_backward(F, torch, 8, 2048, 2048, 20, 3, 5)
         log("bench: forward transforms of every configuration, warm and cold")
         result["configs"] = time_configs(F, torch, 20)
+        # One 4096^2 forward transform against the HBM roofline: two passes that
+        # each read and write every point once (32 algorithmic bytes per point).
+        one = result["configs"]["4096x4096 forward"]
+        alg = 2 * BYTES_PER_POINT_PER_PASS * 4096 * 4096
+        result["forward_4096_roofline"] = {
+            "algorithmic_bytes": alg, "peak_gbps": HBM_PEAK_GBS,
+            "cold_ms": one["cold"]["median_ms"], "warm_ms": one["warm"]["median_ms"],
+            "frac_cold": round(alg / (one["cold"]["median_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "frac_warm": round(alg / (one["warm"]["median_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
         log("bench: device copy bandwidth, 4096 x 4096 complex64")
         result["device_copy"] = device_copy_gbps(torch, rows, cols)
         log("bench: energy per transform (1024 x 1024 and 4096 x 4096)")
