@@ -341,3 +341,32 @@ def test_few_tiles_column_kernel(F, shape, mode, monkeypatch):
         assert err_f <= TOL and err_i <= TOL
     finally:
         plan.close()
+
+
+@pytest.mark.parametrize("shape", [(4096, 1024), (1024, 4096)], ids=lambda s: "%dx%d" % s)
+def test_exec_pass_split_plan(F, shape):
+    """fft2d_exec_pass 0 then 1 with the same arguments equals fft2d_exec, for a
+    split plan called out of place (the intermediate lives in the output) and
+    in place (it goes through the plan's work buffer)."""
+    import torch
+    say("case exec_pass split %dx%d" % shape)
+    x = dev(synth.complex_grid(70, shape))
+    plan = F.Plan(1, *shape)
+    try:
+        assert "split=1 " not in plan.describe(), plan.describe()
+        s = int(torch.cuda.current_stream().cuda_stream)
+        ref = plan(x, F.FORWARD)
+        y = torch.empty_like(x)
+        F.fft2d_exec_pass(plan.handle, x.data_ptr(), y.data_ptr(), F.FORWARD, 0, s)
+        F.fft2d_exec_pass(plan.handle, x.data_ptr(), y.data_ptr(), F.FORWARD, 1, s)
+        w = x.clone()
+        F.fft2d_exec_pass(plan.handle, w.data_ptr(), w.data_ptr(), F.FORWARD, 0, s)
+        F.fft2d_exec_pass(plan.handle, w.data_ptr(), w.data_ptr(), F.FORWARD, 1, s)
+        torch.cuda.synchronize()
+        assert torch.equal(y, ref)
+        assert torch.equal(w, ref)
+        err = rel_l2(host(ref), oracle.fft2_forward(host(x)))
+        say("exec_pass split %dx%d rel_l2=%.3e" % (shape + (err,)))
+        assert err <= TOL
+    finally:
+        plan.close()
