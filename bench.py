@@ -139,8 +139,9 @@ def time_plain(F, torch, rows, cols, steps, warmup, seed):
     """Forward + inverse round trip. The step time comes from `steps` steps of
     two fft2d_exec calls with nothing else on the stream; the per-pass
     durations from a second run of `steps` steps launched pass by pass with
-    HIP events between the passes (markers that would otherwise add their
-    own gaps to the step time)."""
+    fft2d_exec_pass_timed, whose start and stop events are bound to the pass's
+    kernel (hipExtLaunchKernel): each pair spans that kernel alone, and no
+    marker packet sits between the launches."""
     import synth
     x_h = synth.complex_grid(seed, (rows, cols))
     x = torch.from_numpy(x_h).to("cuda")
@@ -155,16 +156,11 @@ def time_plain(F, torch, rows, cols, steps, warmup, seed):
         F.fft2d_exec(plan.handle, xp, yp, F.FORWARD, sh)
         F.fft2d_exec(plan.handle, yp, zp, F.INVERSE, sh)
 
-    def step(evs=None):
-        if evs: evs[0].record(stream)
-        F.fft2d_exec_pass(plan.handle, xp, yp, F.FORWARD, 0, sh)
-        if evs: evs[1].record(stream)
-        F.fft2d_exec_pass(plan.handle, xp, yp, F.FORWARD, 1, sh)
-        if evs: evs[2].record(stream)
-        F.fft2d_exec_pass(plan.handle, yp, zp, F.INVERSE, 0, sh)
-        if evs: evs[3].record(stream)
-        F.fft2d_exec_pass(plan.handle, yp, zp, F.INVERSE, 1, sh)
-        if evs: evs[4].record(stream)
+    passes = ((xp, yp, F.FORWARD, 0), (xp, yp, F.FORWARD, 1), (yp, zp, F.INVERSE, 0), (yp, zp, F.INVERSE, 1))
+
+    def step_timed(evs):
+        for (src, dst, direction, index), (a, b) in zip(passes, evs):
+            F.fft2d_exec_pass_timed(plan.handle, src, dst, direction, index, a.cuda_event, b.cuda_event, sh)
 
     for _ in range(warmup):
         step_plain()
@@ -174,13 +170,19 @@ def time_plain(F, torch, rows, cols, steps, warmup, seed):
         step_plain()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    # per-pass durations: the same steps, each pass between HIP events on the stream it runs on
-    events = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(steps)]
+    # per-pass durations: the same steps, each pass kernel with its own pair of HIP events on the stream it
+    # runs on (each event is recorded once first, which creates it and gives torch a handle to pass on)
+    events = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(4)]
+              for _ in range(steps)]
+    for evs in events:
+        for a, b in evs:
+            a.record(stream)
+            b.record(stream)
     torch.cuda.synchronize()
     for i in range(steps):
-        step(events[i])
+        step_timed(events[i])
     torch.cuda.synchronize()
-    per = np.array([[events[i][j].elapsed_time(events[i][j + 1]) for j in range(4)] for i in range(steps)])
+    per = np.array([[a.elapsed_time(b) for a, b in events[i]] for i in range(steps)])
     # correctness of what was timed: round trip error, computed on the GPU
     rt = float(torch.linalg.vector_norm(z - x) / torch.linalg.vector_norm(x))
     y_h = y.cpu().numpy()

@@ -193,6 +193,21 @@ fft2d_status fft2d_backward(fft2d_plan_t plan, const void* grad_out, void* grad_
  */
 fft2d_status fft2d_exec_pass(fft2d_plan_t plan, const void* in, void* out, int direction, int pass, void* stream);
 
+/*
+ * fft2d_exec_pass_timed -- fft2d_exec_pass with timing: the same pass, same
+ * arguments and results, launched with start_event and stop_event bound to the
+ * pass's kernel launch (hipExtLaunchKernel), so that the elapsed time between
+ * the two events (hipEventElapsedTime) is the kernel's own execution time,
+ * without the marker packets that recording events between launches adds.
+ * start_event and stop_event are hipEvent_t handles created by the caller
+ * (with timing enabled) and still owned by it; both must be non-null
+ * (FFT2D_ERR_NULL_POINTER). The pass must be a single launch: a plan whose
+ * batch holds more than 2^31 points returns FFT2D_ERR_INVALID_SIZE. Other
+ * errors as fft2d_exec_pass. Like it, this only enqueues work on `stream`.
+ */
+fft2d_status fft2d_exec_pass_timed(fft2d_plan_t plan, const void* in, void* out, int direction, int pass,
+                                   void* start_event, void* stop_event, void* stream);
+
 /* fft2d_destroy -- free a plan and its device memory. NULL is a no-op. Waits for
  * no stream: the caller must make sure no enqueued work still uses the plan. */
 fft2d_status fft2d_destroy(fft2d_plan_t plan);

@@ -40,7 +40,8 @@ STATUS_NAMES = {
 }
 
 # Every symbol the public header declares.
-EXPORTS = ("fft2d_plan", "fft2d_plan_batched", "fft2d_exec", "fft2d_exec_pass", "fft2d_exec_batched",
+EXPORTS = ("fft2d_plan", "fft2d_plan_batched", "fft2d_exec", "fft2d_exec_pass", "fft2d_exec_pass_timed",
+           "fft2d_exec_batched",
            "fft2d_backward", "fft2d_destroy", "fft2d_status_string", "fft2d_last_error", "fft2d_plan_describe",
            "fft2d_plan_twiddles", "fft2d_version")
 
@@ -65,6 +66,7 @@ def _load():
     lib.fft2d_plan_batched.argtypes = [pp, i64, ctypes.POINTER(i64), ctypes.POINTER(i64)]
     lib.fft2d_exec.argtypes = [vp, vp, vp, ci, vp]
     lib.fft2d_exec_pass.argtypes = [vp, vp, vp, ci, ci, vp]
+    lib.fft2d_exec_pass_timed.argtypes = [vp, vp, vp, ci, ci, vp, vp, vp]
     lib.fft2d_exec_batched.argtypes = [vp, vp, vp, ci, vp]
     lib.fft2d_backward.argtypes = [vp, vp, vp, ci, vp]
     lib.fft2d_destroy.argtypes = [vp]
@@ -76,7 +78,8 @@ def _load():
     lib.fft2d_plan_twiddles.argtypes = [vp, ci, vp, i64, ctypes.POINTER(i64)]
     lib.fft2d_version.argtypes = []
     lib.fft2d_version.restype = ci
-    for f in ("fft2d_plan", "fft2d_plan_batched", "fft2d_exec", "fft2d_exec_pass", "fft2d_exec_batched", "fft2d_backward",
+    for f in ("fft2d_plan", "fft2d_plan_batched", "fft2d_exec", "fft2d_exec_pass", "fft2d_exec_pass_timed",
+              "fft2d_exec_batched", "fft2d_backward",
               "fft2d_destroy", "fft2d_plan_describe", "fft2d_plan_twiddles"):
         getattr(lib, f).restype = ci
     return lib
@@ -127,6 +130,14 @@ def fft2d_exec(plan: int, in_ptr: int, out_ptr: int, direction: int, stream: int
 
 def fft2d_exec_pass(plan: int, in_ptr: int, out_ptr: int, direction: int, pass_index: int, stream: int = 0) -> None:
     _check(lib.fft2d_exec_pass(plan, in_ptr, out_ptr, int(direction), int(pass_index), stream), "fft2d_exec_pass")
+
+
+def fft2d_exec_pass_timed(plan: int, in_ptr: int, out_ptr: int, direction: int, pass_index: int,
+                          start_event: int, stop_event: int, stream: int = 0) -> None:
+    """start_event, stop_event: hipEvent_t handles (e.g. torch.cuda.Event(enable_timing=True).cuda_event
+    once the event has been recorded); they take the pass kernel's own start and end times."""
+    _check(lib.fft2d_exec_pass_timed(plan, in_ptr, out_ptr, int(direction), int(pass_index), start_event,
+                                     stop_event, stream), "fft2d_exec_pass_timed")
 
 
 def pointer_array(ptrs):

@@ -205,9 +205,10 @@ hipError_t upload_root_table(int64_t n, float2** dev) {
 
 // Enqueue the transform of nb consecutive grids of rows x cols (in, out and
 // work point at the first of them): the whole-grid kernel, or the row pass then
-// the column pass (only_pass = 0 or 1 restricts it to one of them).
+// the column pass (only_pass = 0 or 1 restricts it to one of them; t0, t1:
+// timing events bound to that pass's launch, or null).
 fft2d_status run_grids(const fft2d_plan_s* p, int64_t nb, const float2* in, float2* out, float2* work, int sign,
-                       float scale, hipStream_t s, int only_pass) {
+                       float scale, hipStream_t s, int only_pass, hipEvent_t t0, hipEvent_t t1) {
   const int64_t npts = nb * p->rows * p->cols;
   hipError_t e;
   if (!p->row_k && !p->col_k) {
@@ -247,7 +248,7 @@ fft2d_status run_grids(const fft2d_plan_s* p, int64_t nb, const float2* in, floa
       a.m2 = p->m2;
       a.scale = 1.0f;
       a.nblocks = (int)(nb * p->m2);
-      e = p->row_k->launch(a, sign, s);
+      e = p->row_k->launch(a, sign, s, t0, t1);
       if (e != hipSuccess) return hip_fail(e, "row pass (combine) launch");
     }
     if (only_pass != 0) {
@@ -263,7 +264,7 @@ fft2d_status run_grids(const fft2d_plan_s* p, int64_t nb, const float2* in, floa
       a.m2 = p->m2;
       a.scale = scale;
       a.nblocks = pass_blocks(*p->col_k, a.nvec);
-      e = p->col_k->launch(a, sign, s);
+      e = p->col_k->launch(a, sign, s, t0, t1);
       if (e != hipSuccess) return hip_fail(e, "column pass launch");
     }
     return FFT2D_OK;
@@ -281,7 +282,7 @@ fft2d_status run_grids(const fft2d_plan_s* p, int64_t nb, const float2* in, floa
     a.m1 = 1;
     a.scale = p->col_k ? 1.0f : scale;
     a.nblocks = pass_blocks(*p->row_k, a.nvec);
-    e = p->row_k->launch(a, sign, s);
+    e = p->row_k->launch(a, sign, s, only_pass == 0 ? t0 : nullptr, only_pass == 0 ? t1 : nullptr);
     if (e != hipSuccess) return hip_fail(e, "row pass launch");
     src = out;
   }
@@ -297,7 +298,7 @@ fft2d_status run_grids(const fft2d_plan_s* p, int64_t nb, const float2* in, floa
     a.m1 = 1;
     a.scale = scale;
     a.nblocks = pass_blocks(*p->col_k, a.nvec);
-    e = p->col_k->launch(a, sign, s);
+    e = p->col_k->launch(a, sign, s, only_pass == 1 ? t0 : nullptr, only_pass == 1 ? t1 : nullptr);
     if (e != hipSuccess) return hip_fail(e, "column pass launch");
   }
   return FFT2D_OK;
@@ -310,14 +311,14 @@ constexpr int64_t kMaxLaunchPoints = int64_t(1) << 31;
 
 // Enqueue the transform of the plan's whole batch.
 fft2d_status run_uniform(const fft2d_plan_s* p, const float2* in, float2* out, int sign, float scale,
-                         hipStream_t s, int only_pass = -1) {
+                         hipStream_t s, int only_pass = -1, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr) {
   const int64_t per = p->rows * p->cols;
   const int64_t chunk = std::max<int64_t>(1, kMaxLaunchPoints / per);
   for (int64_t b0 = 0; b0 < p->batch; b0 += chunk) {
     const int64_t nb = std::min(chunk, p->batch - b0);
     const int64_t off = b0 * per;
     const fft2d_status st =
-        run_grids(p, nb, in + off, out + off, p->work ? p->work + off : nullptr, sign, scale, s, only_pass);
+        run_grids(p, nb, in + off, out + off, p->work ? p->work + off : nullptr, sign, scale, s, only_pass, t0, t1);
     if (st != FFT2D_OK) return st;
   }
   return FFT2D_OK;
@@ -497,21 +498,41 @@ fft2d_status fft2d_backward(fft2d_plan_t plan, const void* grad_out, void* grad_
   return run_uniform(plan, (const float2*)grad_out, (float2*)grad_in, sign, scale, (hipStream_t)stream);
 }
 
-fft2d_status fft2d_exec_pass(fft2d_plan_t plan, const void* in, void* out, int direction, int pass, void* stream) {
+namespace {
+
+// Shared by fft2d_exec_pass and fft2d_exec_pass_timed.
+fft2d_status exec_one_pass(fft2d_plan_t plan, const void* in, void* out, int direction, int pass, void* stream,
+                           hipEvent_t t0, hipEvent_t t1, const char* name) {
   if (!plan) return fail(FFT2D_ERR_NULL_POINTER, "plan is NULL");
   if (!is_live(plan)) return fail(FFT2D_ERR_INVALID_PLAN, "plan handle is not live");
-  if (plan->kind != kUniform) return fail(FFT2D_ERR_WRONG_PLAN_KIND, "batched plan passed to fft2d_exec_pass");
+  if (plan->kind != kUniform) return fail(FFT2D_ERR_WRONG_PLAN_KIND, std::string("batched plan passed to ") + name);
   if (fft2d_status dst = check_device(plan); dst != FFT2D_OK) return dst;
   if (direction != FFT2D_FORWARD && direction != FFT2D_INVERSE)
     return fail(FFT2D_ERR_INVALID_DIRECTION, "direction must be FFT2D_FORWARD (-1) or FFT2D_INVERSE (+1)");
   if (pass != 0 && pass != 1) return fail(FFT2D_ERR_INVALID_DIRECTION, "pass must be 0 (rows) or 1 (columns)");
   if ((pass == 0 && !plan->row_k) || (pass == 1 && !plan->col_k))
     return fail(FFT2D_ERR_INVALID_SIZE, "the plan has no such pass (that dimension has length 1)");
-  const int64_t bytes = plan->batch * plan->rows * plan->cols * 8;
+  const int64_t per = plan->rows * plan->cols;
+  if ((t0 != nullptr || t1 != nullptr) && plan->batch > std::max<int64_t>(1, kMaxLaunchPoints / per))
+    return fail(FFT2D_ERR_INVALID_SIZE, "a timed pass must be one launch (batch of at most 2^31 points)");
+  const int64_t bytes = plan->batch * per * 8;
   fft2d_status st = check_data_ptrs(in, out, bytes);
   if (st != FFT2D_OK) return st;
-  const float scale = direction == FFT2D_INVERSE ? (float)(1.0 / (double)(plan->rows * plan->cols)) : 1.0f;
-  return run_uniform(plan, (const float2*)in, (float2*)out, direction, scale, (hipStream_t)stream, pass);
+  const float scale = direction == FFT2D_INVERSE ? (float)(1.0 / (double)per) : 1.0f;
+  return run_uniform(plan, (const float2*)in, (float2*)out, direction, scale, (hipStream_t)stream, pass, t0, t1);
+}
+
+}  // namespace
+
+fft2d_status fft2d_exec_pass(fft2d_plan_t plan, const void* in, void* out, int direction, int pass, void* stream) {
+  return exec_one_pass(plan, in, out, direction, pass, stream, nullptr, nullptr, "fft2d_exec_pass");
+}
+
+fft2d_status fft2d_exec_pass_timed(fft2d_plan_t plan, const void* in, void* out, int direction, int pass,
+                                   void* start_event, void* stop_event, void* stream) {
+  if (!start_event || !stop_event) return fail(FFT2D_ERR_NULL_POINTER, "start_event and stop_event must be events");
+  return exec_one_pass(plan, in, out, direction, pass, stream, (hipEvent_t)start_event, (hipEvent_t)stop_event,
+                       "fft2d_exec_pass_timed");
 }
 
 fft2d_status fft2d_exec_batched(fft2d_plan_t plan, const void* const* in, void* const* out, int direction,

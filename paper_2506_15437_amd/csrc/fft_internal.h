@@ -41,7 +41,10 @@ struct PassArgs {
 
 // One compiled pass kernel: a length-L FFT with a fixed radix schedule,
 // E points per thread, C vectors per workgroup, exchanged through LDS in Q
-// rounds. `launch` enqueues it with the given exponent sign (-1 or +1).
+// rounds. `launch` enqueues it with the given exponent sign (-1 or +1). When
+// t0 or t1 is not null the launch goes through hipExtLaunchKernel with them as
+// its start and stop events, which then carry the kernel's own begin and end
+// times (no marker packets between the kernel and its neighbours).
 struct PassKernel {
   int L, E, T, C, Q, threads;
   int colmode;
@@ -51,7 +54,7 @@ struct PassKernel {
   int npass;
   int radix[kMaxPasses];
   size_t lds_bytes;
-  hipError_t (*launch)(const PassArgs&, int dir, hipStream_t);
+  hipError_t (*launch)(const PassArgs&, int dir, hipStream_t, hipEvent_t t0, hipEvent_t t1);
 };
 
 // One compiled whole-grid kernel: the 2D transform of `rows` x `cols` grids,

@@ -37,6 +37,8 @@
 
 #include "fft_internal.h"
 
+#include <hip/hip_ext.h>
+
 #include <type_traits>
 
 namespace fft2d {
@@ -604,15 +606,31 @@ __global__ __launch_bounds__(KR::THREADS) void grid_kernel(PassArgs a) {
   grid_tile<KR, KC, DIR>(src, dst, tr, tc, io, lds);
 }
 
+// Launch through hipExtLaunchKernel with start and stop events, which then
+// take the kernel's own begin and end times.
+inline hipError_t launch_timed(void (*kernel)(PassArgs), const PassArgs& a, int threads, hipStream_t s,
+                               hipEvent_t t0, hipEvent_t t1) {
+  PassArgs copy = a;
+  void* args[] = {&copy};
+  return hipExtLaunchKernel(reinterpret_cast<const void*>(kernel), dim3(a.nblocks), dim3(threads), args, 0, s,
+                            t0, t1, 0);
+}
+
 template <class K, int WPE, bool NT>
-hipError_t launch_pass(const PassArgs& a, int dir, hipStream_t s) {
+hipError_t launch_pass(const PassArgs& a, int dir, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
+  if (t0 != nullptr || t1 != nullptr)
+    return launch_timed(dir < 0 ? pass_kernel<K, -1, NT, WPE> : pass_kernel<K, +1, NT, WPE>, a, K::THREADS, s,
+                        t0, t1);
   if (dir < 0) hipLaunchKernelGGL((pass_kernel<K, -1, NT, WPE>), dim3(a.nblocks), dim3(K::THREADS), 0, s, a);
   else hipLaunchKernelGGL((pass_kernel<K, +1, NT, WPE>), dim3(a.nblocks), dim3(K::THREADS), 0, s, a);
   return hipGetLastError();
 }
 
 template <class K, int WPE, bool NT>
-hipError_t launch_rowc(const PassArgs& a, int dir, hipStream_t s) {
+hipError_t launch_rowc(const PassArgs& a, int dir, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
+  if (t0 != nullptr || t1 != nullptr)
+    return launch_timed(dir < 0 ? rowc_kernel<K, -1, WPE, 0, NT> : rowc_kernel<K, +1, WPE, 0, NT>, a, K::THREADS,
+                        s, t0, t1);
   if (dir < 0) hipLaunchKernelGGL((rowc_kernel<K, -1, WPE, 0, NT>), dim3(a.nblocks), dim3(K::THREADS), 0, s, a);
   else hipLaunchKernelGGL((rowc_kernel<K, +1, WPE, 0, NT>), dim3(a.nblocks), dim3(K::THREADS), 0, s, a);
   return hipGetLastError();

@@ -370,3 +370,42 @@ def test_exec_pass_split_plan(F, shape):
         assert err <= TOL
     finally:
         plan.close()
+
+
+@pytest.mark.parametrize("shape", [(4096, 4096), (64, 2048)], ids=lambda s: "%dx%d" % s)
+def test_exec_pass_timed(F, shape):
+    """fft2d_exec_pass_timed gives the same results as fft2d_exec_pass, bit for
+    bit (a split plan and a plain one), and its events, bound to the pass's
+    kernel, span a positive time no longer than events recorded around the
+    same launch."""
+    import torch
+    say("case exec_pass_timed %dx%d" % shape)
+    x = dev(synth.complex_grid(71, shape))
+    plan = F.Plan(1, *shape)
+    try:
+        stream = torch.cuda.current_stream()
+        s = int(stream.cuda_stream)
+        ref = plan(x, F.FORWARD)
+        y = torch.empty_like(x)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(8)]
+        for e in ev:
+            e.record(stream)
+        torch.cuda.synchronize()
+        kernel_ms, outer_ms = [], []
+        for index in (0, 1):
+            a, b, outer_a, outer_b = ev[4 * index:4 * index + 4]
+            outer_a.record(stream)
+            F.fft2d_exec_pass_timed(plan.handle, x.data_ptr(), y.data_ptr(), F.FORWARD, index,
+                                    a.cuda_event, b.cuda_event, s)
+            outer_b.record(stream)
+            torch.cuda.synchronize()
+            kernel_ms.append(a.elapsed_time(b))
+            outer_ms.append(outer_a.elapsed_time(outer_b))
+        assert torch.equal(y, ref)
+        say("exec_pass_timed %dx%d kernel ms %s, between outer markers %s" % (shape + (kernel_ms, outer_ms)))
+        for k, o in zip(kernel_ms, outer_ms):
+            assert 0.0 < k <= o * 1.02 + 1e-3
+        with pytest.raises(F.Fft2dError):
+            F.fft2d_exec_pass_timed(plan.handle, x.data_ptr(), y.data_ptr(), F.FORWARD, 0, 0, ev[1].cuda_event, s)
+    finally:
+        plan.close()
