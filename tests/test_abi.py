@@ -79,6 +79,14 @@ def test_exec_rejects_null_and_dead_plans(L):
     assert L.lib.fft2d_exec(bogus, 8, 8, -1, None) == 8
     assert "not live" in L.last_error()
     assert L.lib.fft2d_exec_batched(bogus, None, None, -1, None) == 8
+    assert L.lib.fft2d_exec_pass(None, 8, 8, -1, 0, None) == 1
+    assert L.lib.fft2d_exec_pass(bogus, 8, 8, -1, 0, None) == 8
+    # the timed pass checks its events first, then the plan like fft2d_exec_pass
+    assert L.lib.fft2d_exec_pass_timed(bogus, 8, 8, -1, 0, None, 16, None) == 1
+    assert L.lib.fft2d_exec_pass_timed(bogus, 8, 8, -1, 0, 16, None, None) == 1
+    assert "event" in L.last_error()
+    assert L.lib.fft2d_exec_pass_timed(None, 8, 8, -1, 0, 16, 16, None) == 1
+    assert L.lib.fft2d_exec_pass_timed(bogus, 8, 8, -1, 0, 16, 16, None) == 8
     assert L.lib.fft2d_destroy(bogus) == 8
     assert L.lib.fft2d_destroy(None) == 0
     buf = ctypes.create_string_buffer(16)
