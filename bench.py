@@ -6,8 +6,8 @@ One step = forward 2D FFT (row pass + column pass) then inverse 2D FFT (row
 pass + column pass), out of place: x -> y -> z. Prints ONE JSON line:
 GFLOP/s under the 5 N log2 N convention (two transforms per step), the
 effective HBM bandwidth, the roofline of the dominant kernel (algorithmic
-bytes per launch over its mean duration, timed with HIP events on the stream
-the kernels run on), the FP64 oracle timed on the host cores as CPU baseline,
+bytes per launch over its mean duration, timed with HIP events bound to the
+kernel's launch on the stream it runs on), the FP64 oracle timed on the host cores as CPU baseline,
 and the backward (adjoint) and batched forms against the plain path.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
