@@ -372,20 +372,25 @@ def test_exec_pass_split_plan(F, shape):
         plan.close()
 
 
-@pytest.mark.parametrize("shape", [(4096, 4096), (64, 2048)], ids=lambda s: "%dx%d" % s)
+@pytest.mark.parametrize("shape", [(4096, 4096), (64, 2048), (1024, 1024), (64, 64)], ids=lambda s: "%dx%d" % s)
 def test_exec_pass_timed(F, shape):
     """fft2d_exec_pass_timed gives the same results as fft2d_exec_pass, bit for
-    bit (a split plan and a plain one), and its events, bound to the pass's
-    kernel, span a positive time no longer than events recorded around the
-    same launch."""
+    bit (a split plan, a plain one, one with narrow few-tile passes and a
+    whole-grid plan, whose passes run as two launches here), within the FP32
+    tolerance of the FP64 oracle, and its events, bound to the pass's kernel,
+    span a positive time no longer than events recorded around the same
+    launch."""
     import torch
     say("case exec_pass_timed %dx%d" % shape)
-    x = dev(synth.complex_grid(71, shape))
+    x_h = synth.complex_grid(71, shape)
+    x = dev(x_h)
     plan = F.Plan(1, *shape)
     try:
         stream = torch.cuda.current_stream()
         s = int(stream.cuda_stream)
-        ref = plan(x, F.FORWARD)
+        ref = torch.empty_like(x)
+        F.fft2d_exec_pass(plan.handle, x.data_ptr(), ref.data_ptr(), F.FORWARD, 0, s)
+        F.fft2d_exec_pass(plan.handle, x.data_ptr(), ref.data_ptr(), F.FORWARD, 1, s)
         y = torch.empty_like(x)
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(8)]
         for e in ev:
@@ -402,7 +407,10 @@ def test_exec_pass_timed(F, shape):
             kernel_ms.append(a.elapsed_time(b))
             outer_ms.append(outer_a.elapsed_time(outer_b))
         assert torch.equal(y, ref)
-        say("exec_pass_timed %dx%d kernel ms %s, between outer markers %s" % (shape + (kernel_ms, outer_ms)))
+        err = rel_l2(host(y), oracle.fft2_forward(x_h))
+        say("exec_pass_timed %dx%d rel_l2=%.3e kernel ms %s, between outer markers %s"
+            % (shape + (err, kernel_ms, outer_ms)))
+        assert err <= TOL
         for k, o in zip(kernel_ms, outer_ms):
             assert 0.0 < k <= o * 1.02 + 1e-3
         with pytest.raises(F.Fft2dError):
