@@ -270,6 +270,42 @@ def device_copy_gbps(torch, rows, cols, iters=20):
     return out
 
 
+def vendor_fft_context(F, torch, iters=20):
+    """Context only: torch.fft.fft2 (the ROCm vendor FFT that torch calls) and
+    fft2d_exec on the same inputs, forward, warm medians of `iters` transforms
+    with HIP events around each, and the relative difference of the two
+    results. Nothing of the library's path goes through torch.fft."""
+    import synth
+    stream = torch.cuda.current_stream()
+    sh = int(stream.cuda_stream)
+    res = {}
+    for batch, rows, cols in ((1, 4096, 4096), (1, 8192, 8192), (1, 16384, 2048), (8, 2048, 2048)):
+        shape = (batch, rows, cols) if batch > 1 else (rows, cols)
+        x = torch.from_numpy(synth.complex_grid(1, shape)).to("cuda")
+        y = torch.empty_like(x)
+        plan = F.get_plan(batch, rows, cols, x.device)
+        vendor_out = torch.fft.fft2(x)
+        med = {}
+        for name, fn in (("vendor", lambda: torch.fft.fft2(x)),
+                         ("library", lambda: F.fft2d_exec(plan.handle, x.data_ptr(), y.data_ptr(), F.FORWARD, sh))):
+            for _ in range(3):
+                fn()
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(iters)]
+            for a, b in ev:
+                a.record(stream)
+                fn()
+                b.record(stream)
+            torch.cuda.synchronize()
+            med[name] = float(np.median([a.elapsed_time(b) for a, b in ev]))
+        diff = float(torch.linalg.vector_norm(y - vendor_out) / torch.linalg.vector_norm(vendor_out))
+        name = ("%d x %dx%d forward" % (batch, rows, cols)) if batch > 1 else ("%dx%d forward" % (rows, cols))
+        res[name] = {"torch_fft2_ms": round(med["vendor"], 5), "fft2d_exec_ms": round(med["library"], 5),
+                     "speedup": round(med["vendor"] / med["library"], 2), "rel_l2_difference": diff}
+        del x, y, vendor_out
+    torch.cuda.empty_cache()
+    return res
+
+
 def energy(F, torch, rows, cols, seconds):
     """Energy of forward rows x cols transforms from the GPU's energy counter
     (amdsmi, whole board), over a loop of about `seconds`. None when the
@@ -556,6 +592,8 @@ def main():
         result["energy"] = [energy(F, torch, 1024, 1024, 1.5), energy(F, torch, 4096, 4096, 1.5)]
         log("bench: batched 512 shapes vs 512 plain launches")
         result["batched_vs_plain"] = time_batched(F, torch, 10, 3, 4)
+        log("bench: torch.fft.fft2 (vendor FFT) on the same inputs, context")
+        result["vendor_fft_context"] = vendor_fft_context(F, torch)
 
     if not args.no_cpu:
         log("bench: CPU baseline (FP64 oracle)")

@@ -417,3 +417,18 @@ def test_exec_pass_timed(F, shape):
             F.fft2d_exec_pass_timed(plan.handle, x.data_ptr(), y.data_ptr(), F.FORWARD, 0, 0, ev[1].cuda_event, s)
     finally:
         plan.close()
+
+
+@pytest.mark.parametrize("shape", [(4096, 4096), (256, 2048), (2, 8, 16384)], ids=lambda s: "x".join(map(str, s)))
+def test_agrees_with_torch_fft2(F, shape):
+    """Secondary FP32 sanity check: the library's forward and inverse agree with
+    torch.fft.fft2 / ifft2 (the vendor FFT under torch, default norm: forward
+    unscaled, inverse 1/(M N)) within the FP32 tolerance."""
+    import torch
+    say("case torch.fft %s" % (shape,))
+    x = dev(synth.complex_grid(72, shape))
+    for direction, ref in ((F.FORWARD, torch.fft.fft2(x)), (F.INVERSE, torch.fft.ifft2(x))):
+        y = F.fft2(x) if direction == F.FORWARD else F.ifft2(x)
+        diff = float(torch.linalg.vector_norm(y - ref) / torch.linalg.vector_norm(ref))
+        say("torch.fft %s dir %+d rel diff %.3e" % (shape, direction, diff))
+        assert diff <= TOL
