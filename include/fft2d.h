@@ -203,7 +203,8 @@ fft2d_status fft2d_exec_pass(fft2d_plan_t plan, const void* in, void* out, int d
  * (with timing enabled) and still owned by it; both must be non-null
  * (FFT2D_ERR_NULL_POINTER). The pass must be a single launch: a plan whose
  * batch holds more than 2^31 points returns FFT2D_ERR_INVALID_SIZE. Other
- * errors as fft2d_exec_pass. Like it, this only enqueues work on `stream`.
+ * errors as fft2d_exec_pass. Like it, this only enqueues work on `stream`;
+ * it is a timing aid and not meant to be captured in a HIP graph.
  */
 fft2d_status fft2d_exec_pass_timed(fft2d_plan_t plan, const void* in, void* out, int direction, int pass,
                                    void* start_event, void* stop_event, void* stream);
