@@ -462,29 +462,63 @@ def cpu_baseline(rows, cols, x, budget_s, max_reps, threads=0):
                            "over rows then columns, %.1f s" % (reps, rows, cols, dt)}
 
 
-def cpu_configs(threads=0):
+ORACLE_CASES = [  # (name, shape, seed): the configurations the FP64 oracle also runs, with their bench inputs
+    ("64x64 forward", (64, 64), 0),
+    ("8192 x 64x64 forward", (8192, 64, 64), 6),
+    ("1024x1024 forward", (1024, 1024), 0),
+    ("8192x8192 forward", (8192, 8192), 2),
+    ("16384x2048 forward", (16384, 2048), 3),
+    ("1D: 4096 rows of 16384 points forward", (4096, 1, 16384), 0),
+    ("8 x 2048x2048 forward", (8, 2048, 2048), 5),
+]
+BATCHED_SEED = 4
+
+
+def gpu_forward_outputs(F, torch):
+    """The library's forward transform of every ORACLE_CASES input and of the
+    512-shape batched set (one batched launch), copied to the host."""
+    import synth
+    out = {}
+    for name, shape, seed in ORACLE_CASES:
+        x = torch.from_numpy(synth.complex_grid(seed, shape)).to("cuda")
+        out[name] = F.fft2(x).cpu().numpy()
+        del x
+    xs = [torch.from_numpy(g).to("cuda") for g in synth.batched_grids(BATCHED_SEED, synth.pow2_shapes(BATCHED_SEED, 512))]
+    out["batched"] = [y.cpu().numpy() for y in F.fft2_batched(xs)]
+    del xs
+    torch.cuda.empty_cache()
+    return out
+
+
+def rel_l2(got, ref):
+    return float(np.linalg.norm((got.astype(np.complex128) - ref).ravel()) / np.linalg.norm(ref.ravel()))
+
+
+def cpu_configs(gpu_out, threads=0):
     """The FP64 oracle's forward transform of each configuration once (all host
-    cores), for GPU/CPU context beside the 4096^2 baseline."""
+    cores), for GPU/CPU context beside the 4096^2 baseline, and the relative L2
+    error of the library's result for the same input against it."""
     import oracle
     import synth
-    cases = [("1024x1024 forward", (1024, 1024), 0), ("8192x8192 forward", (8192, 8192), 2),
-             ("16384x2048 forward", (16384, 2048), 3), ("8 x 2048x2048 forward", (8, 2048, 2048), 5)]
     out = {}
-    for name, shape, seed in cases:
+    for name, shape, seed in ORACLE_CASES:
         x = synth.complex_grid(seed, shape)
         t0 = time.perf_counter()
-        oracle.fft2_forward(x, threads)
+        ref = oracle.fft2_forward(x, threads)
         dt = time.perf_counter() - t0
-        batch = shape[0] if len(shape) == 3 else 1
-        out[name] = {"seconds": round(dt, 4), "gflops": round(flops_2d(shape[-2], shape[-1], batch) / dt / 1e9, 2)}
-    shapes = synth.pow2_shapes(4, 512)
-    xs = synth.batched_grids(4, shapes)
+        batch = int(np.prod(shape[:-2])) if len(shape) > 2 else 1
+        out[name] = {"seconds": round(dt, 4), "gflops": round(flops_2d(shape[-2], shape[-1], batch) / dt / 1e9, 2),
+                     "gpu_rel_l2": rel_l2(gpu_out[name], ref)}
+        del x, ref
+    shapes = synth.pow2_shapes(BATCHED_SEED, 512)
+    xs = synth.batched_grids(BATCHED_SEED, shapes)
     t0 = time.perf_counter()
-    for x in xs:
-        oracle.fft2_forward(x, threads)
+    refs = [oracle.fft2_forward(x, threads) for x in xs]
     dt = time.perf_counter() - t0
+    errs = [rel_l2(g, r) for g, r in zip(gpu_out["batched"], refs)]
     out["512 shapes 2^a x 2^b forward"] = {"seconds": round(dt, 4),
-                                           "gflops": round(sum(flops_2d(r, c) for r, c in shapes) / dt / 1e9, 2)}
+                                           "gflops": round(sum(flops_2d(r, c) for r, c in shapes) / dt / 1e9, 2),
+                                           "gpu_rel_l2_max": max(errs)}
     return out
 
 
@@ -603,8 +637,8 @@ def main():
         _, cpu1 = cpu_baseline(rows, cols, r["x"], 4.0, 50, threads=1)
         result["cpu_baseline_1core"] = cpu1
         if not args.no_extras:
-            log("bench: FP64 oracle on the other configurations (context)")
-            result["cpu_oracle_configs"] = cpu_configs()
+            log("bench: FP64 oracle on the other configurations (context, and the library's error on each)")
+            result["cpu_oracle_configs"] = cpu_configs(gpu_forward_outputs(F, torch))
         num = np.linalg.norm((r["y"].astype(np.complex128) - ref).ravel())
         result["fwd_rel_l2_vs_oracle"] = float(num / np.linalg.norm(ref.ravel()))
 
