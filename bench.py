@@ -472,6 +472,7 @@ ORACLE_CASES = [  # (name, shape, seed): the configurations the FP64 oracle also
     ("8 x 2048x2048 forward", (8, 2048, 2048), 5),
 ]
 BATCHED_SEED = 4
+BATCHED_COUNT = 512
 
 
 def gpu_forward_outputs(F, torch):
@@ -483,7 +484,8 @@ def gpu_forward_outputs(F, torch):
         x = torch.from_numpy(synth.complex_grid(seed, shape)).to("cuda")
         out[name] = F.fft2(x).cpu().numpy()
         del x
-    xs = [torch.from_numpy(g).to("cuda") for g in synth.batched_grids(BATCHED_SEED, synth.pow2_shapes(BATCHED_SEED, 512))]
+    xs = [torch.from_numpy(g).to("cuda")
+          for g in synth.batched_grids(BATCHED_SEED, synth.pow2_shapes(BATCHED_SEED, BATCHED_COUNT))]
     out["batched"] = [y.cpu().numpy() for y in F.fft2_batched(xs)]
     del xs
     torch.cuda.empty_cache()
@@ -510,13 +512,13 @@ def cpu_configs(gpu_out, threads=0):
         out[name] = {"seconds": round(dt, 4), "gflops": round(flops_2d(shape[-2], shape[-1], batch) / dt / 1e9, 2),
                      "gpu_rel_l2": rel_l2(gpu_out[name], ref)}
         del x, ref
-    shapes = synth.pow2_shapes(BATCHED_SEED, 512)
+    shapes = synth.pow2_shapes(BATCHED_SEED, BATCHED_COUNT)
     xs = synth.batched_grids(BATCHED_SEED, shapes)
     t0 = time.perf_counter()
     refs = [oracle.fft2_forward(x, threads) for x in xs]
     dt = time.perf_counter() - t0
     errs = [rel_l2(g, r) for g, r in zip(gpu_out["batched"], refs)]
-    out["512 shapes 2^a x 2^b forward"] = {"seconds": round(dt, 4),
+    out["%d shapes 2^a x 2^b forward" % BATCHED_COUNT] = {"seconds": round(dt, 4),
                                            "gflops": round(sum(flops_2d(r, c) for r, c in shapes) / dt / 1e9, 2),
                                            "gpu_rel_l2_max": max(errs)}
     return out

@@ -84,3 +84,24 @@ def test_bench_refuses_more_than_one_gpu():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_cpu_configs_reports_the_error_of_each_result(monkeypatch):
+    """bench.py's per-configuration error report: outputs equal to the oracle's
+    (rounded to complex64) give errors at FP32 rounding level; a planted
+    mistake (a conjugated result) is reported as an error of order one."""
+    import bench
+    import oracle
+    import synth
+    monkeypatch.setattr(bench, "ORACLE_CASES", [("a", (16, 32), 0), ("b", (3, 8, 4), 1), ("c", (2, 1, 64), 2)])
+    monkeypatch.setattr(bench, "BATCHED_COUNT", 3)
+    monkeypatch.setattr(synth, "pow2_shapes", lambda seed, count: [(8, 16), (4, 4), (32, 2)][:count])
+    gpu = {name: oracle.fft2_forward(synth.complex_grid(seed, shape)).astype(np.complex64)
+           for name, shape, seed in bench.ORACLE_CASES}
+    gpu["b"] = np.conj(gpu["b"])
+    gpu["batched"] = [oracle.fft2_forward(x).astype(np.complex64)
+                      for x in synth.batched_grids(bench.BATCHED_SEED, synth.pow2_shapes(bench.BATCHED_SEED, 3))]
+    out = bench.cpu_configs(gpu)
+    assert out["a"]["gpu_rel_l2"] < 1e-7 and out["c"]["gpu_rel_l2"] < 1e-7
+    assert out["b"]["gpu_rel_l2"] > 0.5
+    assert out["3 shapes 2^a x 2^b forward"]["gpu_rel_l2_max"] < 1e-7
