@@ -97,6 +97,30 @@ def summarize_traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir):
     return "\n".join(lines)
 
 
+def summarize_counters(*run_dirs):
+    """Mean per launch of every counter of rocprofv3 --pmc runs (one folder per
+    run), for each pass of the round trip, and the count per wave where the
+    counter counts instructions (wave count SQ_WAVES from the same runs)."""
+    per_pass = {}
+    for d in run_dirs:
+        rows = [r for r in _counter_rows(d) if "fft2d::dev::" in r["Kernel_Name"]]
+        for name in sorted({r["Counter_Name"] for r in rows}):
+            sel = sorted((r for r in rows if r["Counter_Name"] == name), key=lambda r: int(r["Dispatch_Id"]))
+            for i, r in enumerate(sel):
+                e = per_pass.setdefault(PASS_NAMES[i % 4], {"kernel": r["Kernel_Name"]})
+                e.setdefault(name, []).append(float(r["Counter_Value"]))
+    lines = []
+    for p in PASS_NAMES:
+        e = per_pass[p]
+        waves = float(np.mean(e["SQ_WAVES"])) if "SQ_WAVES" in e else None
+        lines.append("pass %s kernel %s" % (p, e["kernel"]))
+        for name in sorted(k for k in e if k != "kernel"):
+            v = float(np.mean(e[name]))
+            extra = ("  per wave %.1f" % (v / waves)) if waves and name.startswith("SQ_INSTS_") else ""
+            lines.append("  %-24s %16.1f  (%d launches)%s" % (name, v, len(e[name]), extra))
+    return "\n".join(lines)
+
+
 def summarize_stats(stats_dir):
     """The fft2d rows of a rocprofv3 --kernel-trace --stats run (kernel_stats.csv)."""
     import csv
@@ -542,11 +566,16 @@ def main():
                     help="only run plain device copies of the 4096x4096 grid (calibrates rocprofv3 byte counters)")
     ap.add_argument("--summarize-traffic", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
                     help="print HBM bytes per pass from four rocprofv3 --pmc output folders, then exit")
+    ap.add_argument("--summarize-counters", nargs="+", metavar="DIR",
+                    help="print the mean of every counter per pass from rocprofv3 --pmc output folders, then exit")
     ap.add_argument("--summarize-stats", metavar="DIR",
                     help="print the kernel rows of a rocprofv3 --kernel-trace --stats output folder, then exit")
     args = ap.parse_args()
     if args.summarize_traffic:
         print(summarize_traffic(*args.summarize_traffic))
+        return
+    if args.summarize_counters:
+        print(summarize_counters(*args.summarize_counters))
         return
     if args.summarize_stats:
         print(summarize_stats(args.summarize_stats))
