@@ -105,3 +105,32 @@ def test_cpu_configs_reports_the_error_of_each_result(monkeypatch):
     assert out["a"]["gpu_rel_l2"] < 1e-7 and out["c"]["gpu_rel_l2"] < 1e-7
     assert out["b"]["gpu_rel_l2"] > 0.5
     assert out["3 shapes 2^a x 2^b forward"]["gpu_rel_l2_max"] < 1e-7
+
+
+def test_counter_summary_means_per_pass(tmp_path):
+    """--summarize-counters: dispatches assigned to passes in step order, the
+    mean per launch of each counter, instruction counts per wave."""
+    import bench
+    names = ["fft2d::dev::rowc_kernel<a, -1>", "fft2d::dev::pass_kernel<b, -1>",
+             "fft2d::dev::rowc_kernel<a, 1>", "fft2d::dev::pass_kernel<b, 1>"]
+    a, b = [], []
+    for step in range(2):
+        for i, n in enumerate(names):
+            d = 10 + step * 4 + i
+            a.append([d, n, "SQ_WAVES", 100.0])
+            a.append([d, n, "SQ_INSTS_VALU", 1000.0 * (i + 1) + 100.0 * step])
+            b.append([d, n, "SQ_WAIT_ANY", 7.0])
+    _write_counters(tmp_path / "a", a + [[1, "some_other_kernel", "SQ_WAVES", 1.0]])
+    _write_counters(tmp_path / "b", b)
+    text = bench.summarize_counters(str(tmp_path / "a"), str(tmp_path / "b"))
+    blocks = {}
+    for line in text.splitlines():
+        f = line.split()
+        if f[0] == "pass":
+            cur = blocks.setdefault(f[1], {})
+        else:
+            cur[f[0]] = f
+    assert float(blocks["fwd_row"]["SQ_INSTS_VALU"][1]) == 1050.0
+    assert blocks["fwd_row"]["SQ_INSTS_VALU"][-1] == "10.5"  # per wave
+    assert float(blocks["inv_col"]["SQ_INSTS_VALU"][1]) == 4050.0
+    assert float(blocks["fwd_col"]["SQ_WAIT_ANY"][1]) == 7.0 and "per" not in blocks["fwd_col"]["SQ_WAIT_ANY"]
