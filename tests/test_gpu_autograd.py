@@ -7,7 +7,7 @@ import pytest
 
 import oracle
 import synth
-from tests.gpu_util import TOL, dev, host, rel_l2, say
+from tests.gpu_util import check, dev, host, say
 
 pytestmark = pytest.mark.gpu
 
@@ -38,9 +38,7 @@ def test_gradient_8x2048x2048_vs_oracle(F):
     loss.backward()
     g = host(xd.grad)
     ref = oracle.weighted_power_grad(x, w)
-    err = rel_l2(g, ref)
-    say("autograd 8x2048^2 gradient rel_l2=%.3e" % err)
-    assert err <= TOL
+    check(g, ref, "autograd 8x2048^2 gradient")
     del xd, loss
     torch.cuda.empty_cache()
 
@@ -101,5 +99,4 @@ def test_adjoint_identity_and_inverse_adjoint(F):
         rhs = np.vdot(fhb, a.astype(np.complex128)).real
         say("adjoint %s dir %d: %.6e vs %.6e" % (shape, direction, lhs, rhs))
         assert abs(lhs - rhs) <= 1e-5 * max(abs(lhs), 1.0)
-        err = rel_l2(fhb, oracle.adjoint(b, direction))
-        assert err <= TOL
+        check(fhb, oracle.adjoint(b, direction), "adjoint %s dir %d vs oracle" % (shape, direction))

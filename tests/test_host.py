@@ -134,3 +134,24 @@ def test_counter_summary_means_per_pass(tmp_path):
     assert blocks["fwd_row"]["SQ_INSTS_VALU"][-1] == "10.5"  # per wave
     assert float(blocks["inv_col"]["SQ_INSTS_VALU"][1]) == 4050.0
     assert float(blocks["fwd_col"]["SQ_WAIT_ANY"][1]) == 7.0 and "per" not in blocks["fwd_col"]["SQ_WAIT_ANY"]
+
+
+def test_element_bound_catches_a_wrong_tile_that_the_norm_misses():
+    """The GPU tests' element-wise bound fails a result whose global relative
+    L2 passes: a 16-column x 1024-row tile of a 4096^2-sized output off by 3e-4
+    relative (planted on the CPU), and a single point off by 1 % of the RMS."""
+    from tests.gpu_util import ELEM_TOL, TOL, errors
+    rng = np.random.default_rng(0)
+    ref = (rng.standard_normal((1024, 1024)) + 1j * rng.standard_normal((1024, 1024))) * 64.0
+    good = ref * (1 + 2e-7)
+    rel, mx = errors(good, ref)
+    assert rel <= TOL and mx <= ELEM_TOL
+    tile = ref.copy()
+    tile[:256, 16:20] *= 1 + 3e-4  # 1/1024 of the points
+    rel, mx = errors(tile, ref)
+    assert rel <= TOL < mx
+    spike = ref.copy()
+    spike[5, 7] += 0.0095 * np.sqrt(np.mean(np.abs(ref) ** 2))
+    rel, mx = errors(spike, ref)
+    assert rel <= TOL < mx
+    assert errors(np.zeros(4), np.zeros(4)) == (0.0, 0.0)
