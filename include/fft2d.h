@@ -158,7 +158,13 @@ fft2d_status fft2d_exec(fft2d_plan_t plan, const void* in, void* out, int direct
  * of polling) so the launch drains even if that were broken. A wait that gives
  * up skips its tile and sets a flag in pinned host memory; the next call on
  * the plan then returns FFT2D_ERR_INCOMPLETE without launching (and clears the
- * flag), since the outputs of the earlier call are incomplete.
+ * flag), since the outputs of the earlier call are incomplete. The last
+ * workgroup of every launch also checks that each XCD's queue was drained (a
+ * queue whose XCD received no workgroup, e.g. under a CU mask on the stream,
+ * leaves its transforms uncomputed) and sets the same flag if not. The
+ * environment variables FFT2D_BATCH_SPIN_LIMIT (-1 gives up every wait) and
+ * FFT2D_BATCH_DRAIN_SLACK (raises the pops the drain check expects) force both
+ * reports from the host, for tests.
  */
 fft2d_status fft2d_exec_batched(fft2d_plan_t plan, const void* const* in, void* const* out, int direction,
                                 void* stream);

@@ -37,6 +37,7 @@
 // conjugate and scale on store (exact in floating point).
 #include "fft_batched.h"
 #include "fft_pass.hpp"
+#include "fft_schedule.hpp"
 
 #include <algorithm>
 #include <cmath>
@@ -121,11 +122,15 @@ struct BatchDesc {
   int32_t pad;
 };
 
-enum ItemKind { kRowItem = 0, kColItem = 1, kCopyItem = 2, kGridItem = 3 };
+using sched::kColItem;
+using sched::kCopyItem;
+using sched::kGridItem;
+using sched::kMaxQueues;
+using sched::kRowItem;
 
-constexpr int kMaxQueues = 8;
-constexpr int kQueueStride = 32;                     // queue heads 128 bytes apart
-constexpr int kCounterBase = kMaxQueues * kQueueStride;  // first per-transform counter
+constexpr int kQueueStride = 32;                            // queue heads 128 bytes apart
+constexpr int kFinishSlot = kMaxQueues * kQueueStride;      // workgroups that have left the loop
+constexpr int kCounterBase = (kMaxQueues + 1) * kQueueStride;  // first per-transform counter
 constexpr int kXccIdReg = (3 << 11) | 20;            // hwreg(HW_REG_XCC_ID, 0, 4)
 
 struct BatchArgs {
@@ -134,8 +139,10 @@ struct BatchArgs {
   const uint32_t* groups;   // group g covers items [groups[g], groups[g + 1])
   int qbeg[kMaxQueues + 1];  // queue x owns groups [qbeg[x], qbeg[x + 1])
   int nq;                   // number of queues (XCDs)
-  unsigned* counters;       // [x * kQueueStride] head of queue x, [kCounterBase + f] finished row items of f
-  unsigned* err_host;       // pinned host word, set to 1 when a bounded wait gives up
+  unsigned* counters;       // [x * kQueueStride] head of queue x, [kFinishSlot] workgroups done,
+                            // [kCounterBase + f] finished row items of f
+  unsigned* err_host;       // pinned host word: 1 when a bounded wait gave up, 2 when a queue was left undrained
+  int drain_slack;          // added to every queue's group count in the drain check (0; > 0 only in tests)
   const float2* tw;         // concatenated twiddle tables, cfg id -> offset in tw_off
   int tw_off[kNumCfg];
   int tw_cnt[kNumCfg];
@@ -416,6 +423,27 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
       __syncthreads();  // the LDS of this item is free before the next item starts
     }
   }
+  // Drain check. A workgroup leaves the loop only after popping past the end
+  // of its queue, so a queue that any workgroup served was popped at least
+  // once per group. The last workgroup to leave reads every head; a queue
+  // with fewer pops than groups had no workgroup (its XCD received none of
+  // this launch's workgroups) and its transforms were not computed: the host
+  // flag makes the plan's next call return FFT2D_ERR_INCOMPLETE. Both reads
+  // are atomics at agent scope, so they see every other workgroup's pops
+  // (each of which returned before that workgroup's increment was issued).
+  if (threadIdx.x == 0) {
+    const unsigned prev = __hip_atomic_fetch_add(&a.counters[kFinishSlot], 1u, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+    if (prev + 1u == gridDim.x) {
+      bool undrained = false;
+      for (int x = 0; x < a.nq; ++x) {
+        const unsigned h = __hip_atomic_fetch_add(&a.counters[x * kQueueStride], 0u, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
+        if ((int64_t)h < (int64_t)(a.qbeg[x + 1] - a.qbeg[x]) + a.drain_slack) undrained = true;
+      }
+      if (undrained) __hip_atomic_store(a.err_host, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+  }
 }
 
 // ---------------------------------------------------------------- host side
@@ -502,6 +530,7 @@ struct BatchedPlan {
   int twc_off[16] = {};       // offset of W_M^j (j < M) in d_tw, index log2 M (split transforms)
   unsigned* h_err = nullptr;  // pinned, coherent: written by the kernel when a wait gives up
   int max_spins = 0;
+  int drain_slack = 0;
   float2* d_tw = nullptr;
   int tw_off[kNumCfg] = {};
   hipStream_t cap_stream = nullptr;
@@ -527,105 +556,26 @@ void set_desc_ptrs(BatchedPlan* bp, int64_t i, const float2* in, float2* out) {
 
 namespace {
 
-struct Schedule {
-  std::vector<uint2> items;
-  std::vector<uint32_t> groups;  // item index where each group starts, plus the end
-  int qbeg[kMaxQueues + 1] = {};
-};
-
-// Points one item moves (its data size / 8 bytes): tiles t0 .. t0 + cnt - 1.
-// A split transform's column vectors are its m1 * N columns of M / m1 points.
-int64_t item_points(const BatchedPlan& bp, const PassKernel* tab, int f, int kind, int t0, int cnt) {
-  const int64_t M = bp.rows[(size_t)f], N = bp.cols[(size_t)f], m1 = bp.m1[(size_t)f];
-  if (kind == kCopyItem) return 1;
-  if (kind == kGridItem) return M * N;
-  if (kind == kRowItem) {
-    const int64_t C = tab[bp.row_cfg[(size_t)f]].C;
-    return std::min<int64_t>(C * cnt, M - (int64_t)t0 * C) * N;
+// The scheduler's view of the plan's transforms.
+std::vector<sched::Shape> sched_shapes(const BatchedPlan& bp) {
+  const PassKernel* tab = cfg_table();
+  std::vector<sched::Shape> v((size_t)bp.count);
+  for (int64_t i = 0; i < bp.count; ++i) {
+    sched::Shape& s = v[(size_t)i];
+    s.rows = bp.rows[(size_t)i];
+    s.cols = bp.cols[(size_t)i];
+    s.m1 = bp.m1[(size_t)i];
+    s.grid = bp.grid[(size_t)i];
+    s.nrow = bp.nrow[(size_t)i];
+    s.ncol = bp.ncol[(size_t)i];
+    s.row_c = std::max(1, tab[bp.row_cfg[(size_t)i]].C);
+    s.col_c = std::max(1, tab[bp.col_cfg[(size_t)i]].C);
   }
-  const int64_t C = tab[bp.col_cfg[(size_t)f]].C;
-  return std::min<int64_t>(C * cnt, m1 * N - (int64_t)t0 * C) * (M / m1);
+  return v;
 }
 
-// Build the queues. Transforms go to the XCD with the least assigned points
-// (largest first). Within a queue, order 0 lists every row item and then every
-// column item (largest transforms first); order 1 works in chunks of about
-// 16 MiB per queue: a chunk's row items, then the previous chunk's column
-// items (which then mostly read data still in the MALL). An item is a run of
-// consecutive tiles of one grid and kind, of about group_kib KiB of data;
-// consecutive items form groups of at least that size; a workgroup pops one
-// group.
-Schedule build_schedule(const BatchedPlan& bp, int order, int group_kib) {
-  const PassKernel* tab = cfg_table();
-  std::vector<int> idx((size_t)bp.count);
-  for (int64_t i = 0; i < bp.count; ++i) idx[(size_t)i] = (int)i;
-  auto pts = [&](int f) { return (int64_t)bp.rows[(size_t)f] * bp.cols[(size_t)f]; };
-  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return pts(a) > pts(b); });
-  std::vector<std::vector<int>> q((size_t)bp.nq);
-  std::vector<int64_t> load((size_t)bp.nq, 0);
-  for (int f : idx) {
-    const size_t x = (size_t)(std::min_element(load.begin(), load.end()) - load.begin());
-    q[x].push_back(f);
-    load[x] += pts(f);
-  }
-  Schedule sc;
-  const int64_t target = (int64_t)group_kib * 1024 / 8;
-  // runs of tiles: about `target` points each (at least one tile); counts < 2^16
-  auto runs = [&](int f, int kind, int ntiles, std::vector<uint2>& out) {
-    const int64_t per_tile = std::max<int64_t>(1, item_points(bp, tab, f, kind, 0, 1));
-    const int run = (int)std::max<int64_t>(1, std::min<int64_t>(target / per_tile, 0xffff));
-    for (int t = 0; t < ntiles; t += run)
-      out.push_back(make_uint2((unsigned)f << 2 | (unsigned)kind, (unsigned)t | (unsigned)std::min(run, ntiles - t) << 16));
-  };
-  auto rows_of = [&](int f, std::vector<uint2>& out) {
-    if (bp.rows[(size_t)f] == 1 && bp.cols[(size_t)f] == 1) {
-      out.push_back(make_uint2((unsigned)f << 2 | kCopyItem, 1u << 16));
-      return;
-    }
-    if (bp.grid[(size_t)f]) {
-      out.push_back(make_uint2((unsigned)f << 2 | kGridItem, 1u << 16));
-      return;
-    }
-    runs(f, kRowItem, bp.nrow[(size_t)f], out);
-  };
-  auto cols_of = [&](int f, std::vector<uint2>& out) { runs(f, kColItem, bp.ncol[(size_t)f], out); };
-  for (int x = 0; x < bp.nq; ++x) {
-    std::vector<uint2> items;
-    if (order == 0) {
-      for (int f : q[(size_t)x]) rows_of(f, items);
-      for (int f : q[(size_t)x]) cols_of(f, items);
-    } else {
-      const int64_t chunk_points = (int64_t(16) << 20) / 8;
-      std::vector<int> prev, cur;
-      int64_t acc = 0;
-      for (size_t k = 0; k < q[(size_t)x].size(); ++k) {
-        const int f = q[(size_t)x][k];
-        rows_of(f, items);
-        cur.push_back(f);
-        acc += pts(f);
-        if (acc >= chunk_points || k + 1 == q[(size_t)x].size()) {
-          for (int g : prev) cols_of(g, items);
-          prev.swap(cur);
-          cur.clear();
-          acc = 0;
-        }
-      }
-      for (int g : prev) cols_of(g, items);
-    }
-    sc.qbeg[x] = (int)sc.groups.size();
-    int64_t acc = target;  // open a new group at the first item
-    for (const uint2& it : items) {
-      if (acc >= target) {
-        sc.groups.push_back((uint32_t)sc.items.size());
-        acc = 0;
-      }
-      acc += item_points(bp, tab, (int)(it.x >> 2), (int)(it.x & 3u), (int)(it.y & 0xffffu), (int)(it.y >> 16));
-      sc.items.push_back(it);
-    }
-  }
-  for (int x = bp.nq; x <= kMaxQueues; ++x) sc.qbeg[x] = (int)sc.groups.size();
-  sc.groups.push_back((uint32_t)sc.items.size());
-  return sc;
+sched::Schedule build_schedule(const BatchedPlan& bp, int order, int group_kib) {
+  return sched::build_schedule(sched_shapes(bp), bp.nq, order, group_kib);
 }
 
 hipError_t launch_batched(BatchedPlan* bp, int conj, int grid, hipStream_t s) {
@@ -649,11 +599,12 @@ hipError_t launch_batched(BatchedPlan* bp, int conj, int grid, hipStream_t s) {
   a.fenced = bp->fenced;
   a.err_host = bp->h_err;
   a.max_spins = bp->max_spins;
+  a.drain_slack = bp->drain_slack;
   hipLaunchKernelGGL(batched_kernel, dim3((unsigned)grid), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
 
-hipError_t upload_schedule(BatchedPlan* bp, const Schedule& sc) {
+hipError_t upload_schedule(BatchedPlan* bp, const sched::Schedule& sc) {
   if (bp->d_items) (void)hipFree(bp->d_items);
   if (bp->d_groups) (void)hipFree(bp->d_groups);
   bp->d_items = nullptr;
@@ -663,6 +614,7 @@ hipError_t upload_schedule(BatchedPlan* bp, const Schedule& sc) {
   for (int x = 0; x <= kMaxQueues; ++x) bp->qbeg[x] = sc.qbeg[x];
   hipError_t e = hipMalloc((void**)&bp->d_items, std::max<size_t>(1, sc.items.size()) * sizeof(uint2));
   if (e != hipSuccess) return e;
+  static_assert(sizeof(sched::Item) == sizeof(uint2), "item layout");
   e = hipMemcpy(bp->d_items, sc.items.data(), sc.items.size() * sizeof(uint2), hipMemcpyHostToDevice);
   if (e != hipSuccess) return e;
   e = hipMalloc((void**)&bp->d_groups, sc.groups.size() * sizeof(uint32_t));
@@ -709,7 +661,8 @@ bool cache_lookup(const std::string& key, int* mult, int* order, int* group_kib)
     std::string k;
     int m = 0, o = -1, g = 0;
     if (!(ls >> k >> m >> o >> g)) continue;
-    if (k == key && m >= 1 && m <= 4 && (o == 0 || o == 1) && valid_group_kib(g)) {
+    // grid multipliers 1 ... 3 are the ones the plan's XCC probe checked
+    if (k == key && m >= 1 && m <= 3 && (o == 0 || o == 1) && valid_group_kib(g)) {
       *mult = m;
       *order = o;
       *group_kib = g;
@@ -896,6 +849,13 @@ fft2d_status create_batched(int64_t count, const int64_t* rows, const int64_t* c
     const long v = std::strtol(sl, &end, 10);
     if (end != sl && *end == '\0' && v >= -1 && v <= kMaxSpins) bp->max_spins = (int)v;
   }
+  // FFT2D_BATCH_DRAIN_SLACK (0 ... 2^20) raises the drain check's expected pops per queue, so that
+  // tests can force the undrained-queue report from the host.
+  if (const char* ds = std::getenv("FFT2D_BATCH_DRAIN_SLACK")) {
+    char* end = nullptr;
+    const long v = std::strtol(ds, &end, 10);
+    if (end != ds && *end == '\0' && v >= 0 && v <= (1L << 20)) bp->drain_slack = (int)v;
+  }
   for (int64_t i = 0; i < count; ++i) {
     BatchDesc& d = bp->h_desc[i];
     d.in = nullptr;
@@ -993,9 +953,13 @@ fft2d_status create_batched(int64_t count, const int64_t* rows, const int64_t* c
 
 fft2d_status exec_batched(BatchedPlan* bp, const void* const* in, void* const* out, int direction, hipStream_t s,
                           std::string* err) {
-  // A bounded wait of an earlier execution gave up: its results are incomplete.
-  if (__atomic_exchange_n(bp->h_err, 0u, __ATOMIC_ACQ_REL) != 0u) {
-    *err = "an earlier execution of this batched plan gave up waiting for row items; its outputs are incomplete";
+  // An earlier execution left work undone: its results are incomplete.
+  const unsigned flag = __atomic_exchange_n(bp->h_err, 0u, __ATOMIC_ACQ_REL);
+  if (flag != 0u) {
+    *err = flag == 2u ? "an earlier execution of this batched plan left a queue undrained (no workgroup ran on "
+                        "one of the XCDs); its outputs are incomplete"
+                      : "an earlier execution of this batched plan gave up waiting for row items; its outputs are "
+                        "incomplete";
     return FFT2D_ERR_INCOMPLETE;
   }
   bool changed = bp->last_in.size() != (size_t)bp->count;

@@ -280,3 +280,39 @@ def test_batched_gave_up_wait_is_reported(F, monkeypatch):
         w.report()
     finally:
         plan.close()
+
+
+def test_batched_undrained_queue_is_reported(F, monkeypatch):
+    """The end-of-launch drain check: told by the host to expect more pops per
+    queue than any launch makes (FFT2D_BATCH_DRAIN_SLACK), it reports an
+    undrained queue, and the next call returns FFT2D_ERR_INCOMPLETE once; with
+    the default (0) a full launch reports nothing, over several calls."""
+    import torch
+    monkeypatch.setenv("FFT2D_TUNE", "off")
+    shapes = [(64, 64), (256, 128), (2048, 1024), (16, 4096)]
+    say("case batched drain check")
+    xs_h = synth.batched_grids(16, shapes)
+    xs = [dev(x) for x in xs_h]
+    monkeypatch.setenv("FFT2D_BATCH_DRAIN_SLACK", str(1 << 20))
+    plan = F.BatchedPlan(shapes)
+    try:
+        plan(xs, F.FORWARD)
+        torch.cuda.synchronize()
+        with pytest.raises(F.Fft2dError) as e:
+            plan(xs, F.FORWARD)
+        assert e.value.status == 10 and "undrained" in str(e.value), str(e.value)
+        torch.cuda.synchronize()
+    finally:
+        plan.close()
+    monkeypatch.delenv("FFT2D_BATCH_DRAIN_SLACK")
+    plan = F.BatchedPlan(shapes)
+    try:
+        for _ in range(4):
+            ys = plan(xs, F.FORWARD)
+            torch.cuda.synchronize()
+        w = Worst("batched after drain checks")
+        for x, y, s in zip(xs_h, ys, shapes):
+            w.add(host(y), oracle.fft2_forward(x), s)
+        w.report()
+    finally:
+        plan.close()

@@ -155,3 +155,17 @@ def test_element_bound_catches_a_wrong_tile_that_the_norm_misses():
     rel, mx = errors(spike, ref)
     assert rel <= TOL < mx
     assert errors(np.zeros(4), np.zeros(4)) == (0.0, 0.0)
+
+
+def test_batched_schedule_invariants(tmp_path):
+    """The batched path's scheduler (csrc/fft_schedule.hpp, plain C++) on
+    random shape sets, for every queue count, item order and group size: each
+    tile appears once, a transform's items share one queue with all its row
+    items before its column items, and groups tile the item table
+    (tests/c/schedule_check.cpp)."""
+    exe = str(tmp_path / "schedule_check")
+    src = os.path.join(ROOT, "tests", "c", "schedule_check.cpp")
+    subprocess.run(["g++", "-std=c++17", "-O2", "-Wall", "-Wextra", "-Werror", src, "-o", exe], check=True,
+                   timeout=120)
+    r = subprocess.run([exe, "120"], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0 and r.stdout.startswith("ok "), r.stdout + r.stderr
