@@ -252,6 +252,35 @@ fft2d_status fft2d_plan_describe(fft2d_plan_t plan, char* buf, int64_t buflen);
  */
 fft2d_status fft2d_plan_twiddles(fft2d_plan_t plan, int which, void* host_out, int64_t capacity, int64_t* count);
 
+/* Work-buffer capacity of fft2d_exec_noalloc, in bytes (64 MiB). */
+#define FFT2D_NOALLOC_WORK_BYTES (64 * 1024 * 1024)
+
+/*
+ * fft2d_exec_noalloc -- fft2d_exec without a plan and without any allocation,
+ * for callers that cannot allocate device memory when they transform (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc). It computes exactly what fft2d_exec computes for a plan made by
+ * fft2d_plan(batch, rows, cols) on the current device, with the same kernels
+ * (and the same environment overrides), on caller-owned buffers:
+ *   batch, rows, cols : as for fft2d_plan (FFT2D_ERR_INVALID_SIZE otherwise);
+ *   in, out           : device pointers to batch*rows*cols complex64, 8-byte
+ *                       aligned; in == out allowed, partial overlap rejected;
+ *   direction, stream : as for fft2d_exec.
+ * Instead of plan memory it uses one library-owned device array of
+ * 3*16384*8 bytes of twiddle tables plus FFT2D_NOALLOC_WORK_BYTES of work
+ * buffer, which every GPU the library runs on holds from its first use until
+ * the process ends. Each call first rewrites the tables on `stream` (one small
+ * kernel computing every entry in FP64 and rounding it once to FP32), then
+ * enqueues the passes; it never synchronises and calls no allocating routine.
+ * Only in-place calls of split shapes (see fft2d_plan) need the work buffer:
+ * such a call with batch*rows*cols*8 > FFT2D_NOALLOC_WORK_BYTES returns
+ * FFT2D_ERR_INVALID_SIZE before enqueuing anything. Calls that overlap on one
+ * GPU (several streams or host threads) race on the shared array and must not
+ * be made; calls ordered on one stream are safe.
+ */
+fft2d_status fft2d_exec_noalloc(int64_t batch, int64_t rows, int64_t cols, const void* in, void* out,
+                                int direction, void* stream);
+
 /* Library version as MAJOR*10000 + MINOR*100 + PATCH. */
 int fft2d_version(void);
 

@@ -43,7 +43,7 @@ STATUS_NAMES = {
 EXPORTS = ("fft2d_plan", "fft2d_plan_batched", "fft2d_exec", "fft2d_exec_pass", "fft2d_exec_pass_timed",
            "fft2d_exec_batched",
            "fft2d_backward", "fft2d_destroy", "fft2d_status_string", "fft2d_last_error", "fft2d_plan_describe",
-           "fft2d_plan_twiddles", "fft2d_version")
+           "fft2d_plan_twiddles", "fft2d_exec_noalloc", "fft2d_version")
 
 
 class Fft2dError(RuntimeError):
@@ -76,11 +76,12 @@ def _load():
     lib.fft2d_last_error.restype = ctypes.c_char_p
     lib.fft2d_plan_describe.argtypes = [vp, ctypes.c_char_p, i64]
     lib.fft2d_plan_twiddles.argtypes = [vp, ci, vp, i64, ctypes.POINTER(i64)]
+    lib.fft2d_exec_noalloc.argtypes = [i64, i64, i64, vp, vp, ci, vp]
     lib.fft2d_version.argtypes = []
     lib.fft2d_version.restype = ci
     for f in ("fft2d_plan", "fft2d_plan_batched", "fft2d_exec", "fft2d_exec_pass", "fft2d_exec_pass_timed",
               "fft2d_exec_batched", "fft2d_backward",
-              "fft2d_destroy", "fft2d_plan_describe", "fft2d_plan_twiddles"):
+              "fft2d_destroy", "fft2d_plan_describe", "fft2d_plan_twiddles", "fft2d_exec_noalloc"):
         getattr(lib, f).restype = ci
     return lib
 
@@ -159,6 +160,16 @@ def fft2d_exec_batched(plan: int, in_ptrs, out_ptrs, direction: int, stream: int
 
 def fft2d_backward(plan: int, grad_out_ptr: int, grad_in_ptr: int, forward_direction: int, stream: int = 0) -> None:
     _check(lib.fft2d_backward(plan, grad_out_ptr, grad_in_ptr, int(forward_direction), stream), "fft2d_backward")
+
+
+def fft2d_exec_noalloc(batch: int, rows: int, cols: int, in_ptr: int, out_ptr: int, direction: int,
+                       stream: int = 0) -> None:
+    """fft2d_exec without a plan or any allocation (library-owned device array)."""
+    _check(lib.fft2d_exec_noalloc(int(batch), int(rows), int(cols), in_ptr, out_ptr, int(direction), stream),
+           "fft2d_exec_noalloc")
+
+
+NOALLOC_WORK_BYTES = 64 * 1024 * 1024
 
 
 def fft2d_destroy(plan: int) -> None:

@@ -365,13 +365,7 @@ fft2d_status check_data_ptrs(const void* in, const void* out, int64_t bytes) {
   return FFT2D_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-fft2d_status fft2d_plan(fft2d_plan_t* out, int64_t batch, int64_t rows, int64_t cols) {
-  if (!out) return fail(FFT2D_ERR_NULL_POINTER, "plan output pointer is NULL");
-  *out = nullptr;
+fft2d_status check_shape(int64_t batch, int64_t rows, int64_t cols) {
   if (batch < 1) return fail(FFT2D_ERR_INVALID_SIZE, "batch must be >= 1");
   if (!pow2_in_range(rows) || !pow2_in_range(cols))
     return fail(FFT2D_ERR_INVALID_SIZE, "rows and cols must be powers of two in [1, 16384], got " +
@@ -379,17 +373,16 @@ fft2d_status fft2d_plan(fft2d_plan_t* out, int64_t batch, int64_t rows, int64_t 
   // 2^35 points (256 GiB of complex64) bound every grid-size computation well inside 32 bits
   if (batch > (int64_t(1) << 35) / (rows * cols))
     return fail(FFT2D_ERR_INVALID_SIZE, "batch*rows*cols exceeds 2^35 points");
-  fft2d_plan_s* p = new (std::nothrow) fft2d_plan_s();
-  if (!p) return fail(FFT2D_ERR_OUT_OF_MEMORY, "host allocation failed");
+  return FFT2D_OK;
+}
+
+// Kernel choice of a uniform plan (split factor, pass kernels, whole-grid
+// kernel); host only, no device memory.
+fft2d_status select_kernels(fft2d_plan_s* p, int64_t batch, int64_t rows, int64_t cols) {
   p->kind = kUniform;
   p->batch = batch;
   p->rows = rows;
   p->cols = cols;
-  hipError_t e = hipGetDevice(&p->device);
-  if (e != hipSuccess) {
-    delete p;
-    return hip_fail(e, "hipGetDevice");
-  }
   p->m1 = choose_split(rows, cols);
   p->m2 = rows / p->m1;
   if (p->m1 > 1) {
@@ -410,9 +403,119 @@ fft2d_status fft2d_plan(fft2d_plan_t* out, int64_t batch, int64_t rows, int64_t 
         use_grid_kernel(batch, rows * cols))
       p->grid_k = g;
   }
-  if ((cols > 1 && !p->row_k) || (rows > 1 && !p->col_k)) {
-    delete p;
+  if ((cols > 1 && !p->row_k) || (rows > 1 && !p->col_k))
     return fail(FFT2D_ERR_INVALID_SIZE, "no kernel for this length");
+  return FFT2D_OK;
+}
+
+// ------------------------------------------------------------------------
+// Allocation-free execution (fft2d_exec_noalloc). The twiddle tables and the
+// work buffer of in-place split transforms live in one file-scope device
+// array instead of plan memory: every GPU the library runs on holds one copy
+// of it from the first use of this code object until the process ends. The
+// tables are rewritten on the caller's stream by every call, so calls that
+// overlap on one GPU race on the array.
+constexpr int64_t kNoallocTableSlot = FFT2D_MAX_LEN;  // entries per table (row, column, combine)
+constexpr int64_t kNoallocTablePoints = 3 * kNoallocTableSlot;
+constexpr int64_t kNoallocWorkPoints = FFT2D_NOALLOC_WORK_BYTES / 8;
+static_assert(FFT2D_NOALLOC_WORK_BYTES % 8 == 0, "whole complex64 points");
+
+static __device__ __align__(256) float2 scratch[kNoallocTablePoints + kNoallocWorkPoints];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float2* g_scratch[kMaxDevices] = {};  // device address of `scratch` on each device, once looked up
+
+// The current device's copy of `scratch` (its address is looked up once per
+// device, with that device current; host code never uses the array's name as
+// an address).
+fft2d_status scratch_of_current_device(float2** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(FFT2D_ERR_INVALID_SIZE, "device index " + std::to_string(dev) + " is beyond the library's 64");
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!ptr) return fail(FFT2D_ERR_HIP, "hipGetSymbolAddress(scratch) gave a null address");
+    g_scratch[dev] = static_cast<float2*>(ptr);
+  }
+  *out = g_scratch[dev];
+  return FFT2D_OK;
+}
+
+// One table to fill on the device: a schedule's inter-pass table (npass >= 2;
+// entry (r, k) of pass p >= 1 is exp(-2 pi i k r / (Ns_p R_p)), the layout
+// of fill_twiddles) or, with npass == 0, the root table exp(-2 pi i j / count),
+// j < count. count == 0: nothing.
+struct TableSpec {
+  float2* dst;
+  int count;
+  int npass;
+  int off[kMaxPasses + 1];  // first entry of pass p >= 1; off[npass] = count
+  int ns[kMaxPasses];
+  int radix[kMaxPasses];
+};
+
+TableSpec schedule_spec(const PassKernel* k, float2* dst) {
+  TableSpec t{};
+  t.dst = dst;
+  if (!k) return t;
+  int o = 0, ns = 1;
+  t.npass = k->npass;
+  for (int p = 0; p < k->npass; ++p) {
+    t.off[p] = o;
+    t.ns[p] = ns;
+    t.radix[p] = k->radix[p];
+    if (p > 0) o += ns * (k->radix[p] - 1);
+    ns *= k->radix[p];
+  }
+  t.off[k->npass] = o;
+  t.count = o;
+  if (t.npass < 2) t.count = 0;  // a one-pass schedule has no table
+  return t;
+}
+
+// Every entry from its own angle: sincospi of 2 q / n, exact in FP64 (n is a
+// power of two), then rounded once to FP32.
+__global__ void fill_tables_kernel(TableSpec t0, TableSpec t1, TableSpec t2) {
+  const TableSpec t = blockIdx.y == 0 ? t0 : (blockIdx.y == 1 ? t1 : t2);
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < t.count; i += gridDim.x * blockDim.x) {
+    int64_t q = i, n = t.count;
+    if (t.npass > 0) {
+      int p = 1;
+      while (p + 1 < t.npass && i >= t.off[p + 1]) ++p;
+      const int rel = i - t.off[p];
+      q = (int64_t)(rel % t.ns[p]) * (1 + rel / t.ns[p]);
+      n = (int64_t)t.ns[p] * t.radix[p];
+    }
+    double sn = 0.0, cs = 0.0;
+    sincospi(2.0 * (double)q / (double)n, &sn, &cs);
+    t.dst[i] = make_float2((float)cs, (float)(-sn));
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+fft2d_status fft2d_plan(fft2d_plan_t* out, int64_t batch, int64_t rows, int64_t cols) {
+  if (!out) return fail(FFT2D_ERR_NULL_POINTER, "plan output pointer is NULL");
+  *out = nullptr;
+  if (fft2d_status st = check_shape(batch, rows, cols); st != FFT2D_OK) return st;
+  fft2d_plan_s* p = new (std::nothrow) fft2d_plan_s();
+  if (!p) return fail(FFT2D_ERR_OUT_OF_MEMORY, "host allocation failed");
+  hipError_t e = hipGetDevice(&p->device);
+  if (e != hipSuccess) {
+    delete p;
+    return hip_fail(e, "hipGetDevice");
+  }
+  if (fft2d_status st = select_kernels(p, batch, rows, cols); st != FFT2D_OK) {
+    delete p;
+    return st;
   }
   auto oom_or_hip = [&](hipError_t err, const char* what) {
     free_plan(p);
@@ -633,6 +736,40 @@ fft2d_status fft2d_plan_twiddles(fft2d_plan_t plan, int which, void* host_out, i
     if (e != hipSuccess) return hip_fail(e, "twiddle download");
   }
   return FFT2D_OK;
+}
+
+fft2d_status fft2d_exec_noalloc(int64_t batch, int64_t rows, int64_t cols, const void* in, void* out,
+                                int direction, void* stream) {
+  if (fft2d_status st = check_shape(batch, rows, cols); st != FFT2D_OK) return st;
+  if (direction != FFT2D_FORWARD && direction != FFT2D_INVERSE)
+    return fail(FFT2D_ERR_INVALID_DIRECTION, "direction must be FFT2D_FORWARD (-1) or FFT2D_INVERSE (+1)");
+  const int64_t points = batch * rows * cols;
+  if (fft2d_status st = check_data_ptrs(in, out, points * 8); st != FFT2D_OK) return st;
+  fft2d_plan_s p;  // kernel choice only: its tables and work buffer are the scratch array
+  if (fft2d_status st = select_kernels(&p, batch, rows, cols); st != FFT2D_OK) return st;
+  const bool in_place = static_cast<const void*>(in) == static_cast<const void*>(out);
+  if (p.m1 > 1 && in_place && points > kNoallocWorkPoints)
+    return fail(FFT2D_ERR_INVALID_SIZE,
+                "an in-place call of this shape needs a work buffer of " + std::to_string(points * 8) +
+                    " bytes; the allocation-free entry point has " + std::to_string(kNoallocWorkPoints * 8) +
+                    " (call it out of place, or use fft2d_plan / fft2d_exec)");
+  float2* base = nullptr;
+  if (fft2d_status st = scratch_of_current_device(&base); st != FFT2D_OK) return st;
+  p.tw_row = base;
+  p.tw_col = base + kNoallocTableSlot;
+  p.tw_comb = base + 2 * kNoallocTableSlot;
+  p.work = (p.m1 > 1 && in_place) ? base + kNoallocTablePoints : nullptr;
+  const TableSpec tr = schedule_spec(p.row_k, p.tw_row);
+  const TableSpec tc = schedule_spec(p.col_k, p.tw_col);
+  TableSpec tm{};
+  tm.dst = p.tw_comb;
+  tm.count = p.m1 > 1 ? (int)rows : 0;
+  const hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(fill_tables_kernel, dim3((unsigned)(kNoallocTableSlot / 256), 3), dim3(256), 0, s, tr, tc, tm);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "twiddle table kernel launch");
+  const float scale = direction == FFT2D_INVERSE ? (float)(1.0 / (double)(rows * cols)) : 1.0f;
+  return run_uniform(&p, (const float2*)in, (float2*)out, direction, scale, s);
 }
 
 int fft2d_version(void) { return kVersion; }
