@@ -7,10 +7,14 @@ pass + column pass), out of place: x -> y -> z. Prints ONE JSON line:
 GFLOP/s under the 5 N log2 N convention (two transforms per step), the
 effective HBM bandwidth, the roofline of the dominant kernel (algorithmic
 bytes per launch over its mean duration, timed with HIP events bound to the
-kernel's launch on the stream it runs on), the FP64 oracle timed on the host cores as CPU baseline,
-and the backward (adjoint) and batched forms against the plain path.
+kernel's launch on the stream it runs on), the FP64 oracle timed on the host
+cores as CPU baseline, every configuration's forward transform with its
+passes against their data-movement floors (the same kernels with arithmetic,
+then also the LDS exchanges, switched off), and the backward (adjoint) and
+batched forms against the plain path.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+       python bench.py --only NAME [--steps K] [--warmup W]   (one configuration, for rocprofv3)
 """
 
 from __future__ import annotations
@@ -63,11 +67,58 @@ def _counter_rows(run_dir):
         return list(csv.DictReader(fh))
 
 
-def summarize_traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir):
+def kernel_role(name):
+    """(kind, direction) of a library pass kernel from its demangled name:
+    kind "row" (pass_kernel in row mode, or rowc_kernel) or "col" (pass_kernel
+    in column mode), direction -1 or +1 (the template argument after the
+    configuration); None for any other kernel. A measurement variant (last
+    template argument 1 or 2) has kind "row-probe" / "col-probe"."""
+    import re
+    m = re.search(r"fft2d::dev::(pass_kernel|rowc_kernel)<fft2d::dev::Cfg<([^>]*)>,\s*(-?\d+)([^>]*)>", name)
+    if not m:
+        return None
+    kernel, cfg, sign, rest = m.group(1), [v.strip() for v in m.group(2).split(",")], int(m.group(3)), m.group(4)
+    kind = "col" if (kernel == "pass_kernel" and cfg[4] == "true") else "row"
+    tail = [v.strip() for v in rest.split(",") if v.strip()]
+    if kernel == "pass_kernel" and len(tail) >= 4 and tail[3] in ("1", "2"):
+        kind += "-probe"
+    if kernel == "rowc_kernel" and len(tail) >= 4 and tail[3] in ("1", "2"):
+        kind += "-probe"
+    return kind, (-1 if sign < 0 else 1)
+
+
+# expected (kind, direction) of each pass of the profiled sequences
+ROUND_TRIP_ROLES = {"fwd_row": ("row", -1), "fwd_col": ("col", -1), "inv_row": ("row", 1), "inv_col": ("col", 1)}
+FORWARD_ROLES = {"fwd_row": ("row", -1), "fwd_col": ("col", -1)}
+
+
+def _assign_passes(rows, roles):
+    """Dispatches of the library's pass kernels in dispatch order, each given
+    the pass name whose role it has (the sequence cycles through `roles`);
+    raises ValueError when a dispatch's kernel is not the expected one (an
+    extra or missing dispatch would otherwise shift every later counter onto
+    the wrong pass)."""
+    names = list(roles)
+    sel = [r for r in rows if kernel_role(r["Kernel_Name"]) is not None
+           and not kernel_role(r["Kernel_Name"])[0].endswith("-probe")]
+    sel.sort(key=lambda r: int(r["Dispatch_Id"]))
+    out = []
+    for i, r in enumerate(sel):
+        want = names[i % len(names)]
+        got = kernel_role(r["Kernel_Name"])
+        if got != roles[want]:
+            raise ValueError("dispatch %s (%s) is %s, expected %s for pass %s"
+                             % (r["Dispatch_Id"], r["Kernel_Name"], got, roles[want], want))
+        out.append((want, r))
+    return out
+
+
+def summarize_traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, points=4096 * 4096,
+                      roles=ROUND_TRIP_ROLES, copy_bytes=4096 * 4096 * 8):
     """HBM bytes per launch of each pass from rocprofv3 FETCH_SIZE / WRITE_SIZE
     runs (KiB per dispatch), each scaled by the factor that makes the same
-    counter read the known size of a plain device copy (bench.py --copy-only)."""
-    copy_bytes = 4096 * 4096 * 8  # bytes read, and bytes written, by one copy of the grid
+    counter read the known size of a plain device copy (bench.py --copy-only:
+    `copy_bytes` read and written per copy)."""
     factors = {}
     for name, d in (("FETCH_SIZE", copy_fetch_dir), ("WRITE_SIZE", copy_write_dir)):
         vals = [float(r["Counter_Value"]) for r in _counter_rows(d)
@@ -76,17 +127,15 @@ def summarize_traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir):
         factors[name] = (copy_bytes / 1024.0) / kib
     per_pass = {}
     for name, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
-        rows = [r for r in _counter_rows(d) if "fft2d::dev::" in r["Kernel_Name"] and r["Counter_Name"] == name]
-        rows.sort(key=lambda r: int(r["Dispatch_Id"]))
-        for i, r in enumerate(rows):
-            p = PASS_NAMES[i % 4]
+        rows = [r for r in _counter_rows(d) if r["Counter_Name"] == name]
+        for p, r in _assign_passes(rows, roles):
             per_pass.setdefault(p, {}).setdefault(name, []).append(float(r["Counter_Value"]))
             per_pass[p]["kernel"] = r["Kernel_Name"]
     lines = ["source_hash = %s" % kernel_source_hash(),
              "fetch_factor = %.4f" % factors["FETCH_SIZE"],
              "write_factor = %.4f" % factors["WRITE_SIZE"],
-             "algorithmic_bytes_per_pass = %d" % (BYTES_PER_POINT_PER_PASS * 4096 * 4096)]
-    for p in PASS_NAMES:
+             "algorithmic_bytes_per_pass = %d" % (BYTES_PER_POINT_PER_PASS * points)]
+    for p in roles:
         e = per_pass[p]
         fk = float(np.mean(e["FETCH_SIZE"]))
         wk = float(np.mean(e["WRITE_SIZE"]))
@@ -97,20 +146,20 @@ def summarize_traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir):
     return "\n".join(lines)
 
 
-def summarize_counters(*run_dirs):
+def summarize_counters(*run_dirs, roles=ROUND_TRIP_ROLES):
     """Mean per launch of every counter of rocprofv3 --pmc runs (one folder per
-    run), for each pass of the round trip, and the count per wave where the
-    counter counts instructions (wave count SQ_WAVES from the same runs)."""
+    run), for each pass of the profiled sequence, and the count per wave where
+    the counter counts instructions (wave count SQ_WAVES from the same runs)."""
     per_pass = {}
     for d in run_dirs:
-        rows = [r for r in _counter_rows(d) if "fft2d::dev::" in r["Kernel_Name"]]
+        rows = _counter_rows(d)
         for name in sorted({r["Counter_Name"] for r in rows}):
-            sel = sorted((r for r in rows if r["Counter_Name"] == name), key=lambda r: int(r["Dispatch_Id"]))
-            for i, r in enumerate(sel):
-                e = per_pass.setdefault(PASS_NAMES[i % 4], {"kernel": r["Kernel_Name"]})
+            sel = [r for r in rows if r["Counter_Name"] == name]
+            for p, r in _assign_passes(sel, roles):
+                e = per_pass.setdefault(p, {"kernel": r["Kernel_Name"]})
                 e.setdefault(name, []).append(float(r["Counter_Value"]))
     lines = []
-    for p in PASS_NAMES:
+    for p in roles:
         e = per_pass[p]
         waves = float(np.mean(e["SQ_WAVES"])) if "SQ_WAVES" in e else None
         lines.append("pass %s kernel %s" % (p, e["kernel"]))
@@ -121,17 +170,44 @@ def summarize_counters(*run_dirs):
     return "\n".join(lines)
 
 
+STATS_PROFILE = os.path.join(ROOT, "profiles", "kernel_stats_fft2d_4096x4096_roundtrip.txt")
+
+
 def summarize_stats(stats_dir):
-    """The fft2d rows of a rocprofv3 --kernel-trace --stats run (kernel_stats.csv)."""
+    """The rows of a rocprofv3 --kernel-trace --stats run (kernel_stats.csv),
+    after the hash of the plain path's sources they were taken from."""
     import csv
     with open(os.path.join(stats_dir, "run_kernel_stats.csv"), newline="") as fh:
         rows = list(csv.DictReader(fh))
-    out = ["calls  avg_us   min_us   max_us   total_%  kernel"]
+    out = ["source_hash = %s" % kernel_source_hash(), "calls  avg_us   min_us   max_us   total_%  kernel"]
     for r in rows:
         out.append("%5s %8.2f %8.2f %8.2f %8.2f  %s" % (r["Calls"], float(r["AverageNs"]) / 1e3,
                                                       float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3,
                                                       float(r["Percentage"]), r["Name"]))
     return "\n".join(out)
+
+
+def rocprof_roofline(pass_name, pass_bytes):
+    """The dominant pass's average duration in the committed rocprofv3 kernel
+    statistics of the round trip (the same bench command under rocprofv3), as
+    a roofline fraction; None when the summary is missing or was taken from
+    other kernel sources."""
+    try:
+        with open(STATS_PROFILE) as fh:
+            lines = fh.read().splitlines()
+    except OSError:
+        return None
+    hashes = [l.split()[2] for l in lines if l.startswith("source_hash = ")]
+    if not hashes or hashes[0] != kernel_source_hash():
+        return None
+    want = ROUND_TRIP_ROLES[pass_name]
+    for l in lines:
+        f = l.split(None, 5)
+        if len(f) == 6 and f[0].isdigit() and kernel_role(f[5]) == want:
+            avg_us = float(f[1])
+            return {"avg_us": avg_us, "calls": int(f[0]), "achieved": round(pass_bytes / (avg_us * 1e-6) / 1e9, 1),
+                    "frac": round(pass_bytes / (avg_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
+    return None
 
 
 def measured_traffic(pass_name):
@@ -221,7 +297,65 @@ CONFIGS = [  # (name, batch, rows, cols, seed)
     ("8192x8192 forward", 1, 8192, 8192, 2),
     ("16384x2048 forward", 1, 16384, 2048, 3),
     ("1D: 4096 rows of 16384 points forward", 4096, 1, 16384, 0),
+    ("8 x 2048x2048 forward", 8, 2048, 2048, 5),
 ]
+# --only names: configuration (batch, rows, cols, seed)
+ONLY = {"64x64": (1, 64, 64, 0), "8192x64x64": (8192, 64, 64, 6), "1024x1024": (1, 1024, 1024, 0),
+        "4096x4096": (1, 4096, 4096, 1), "8192x8192": (1, 8192, 8192, 2), "16384x2048": (1, 16384, 2048, 3),
+        "4096x1x16384": (4096, 1, 16384, 0), "8x2048x2048": (8, 2048, 2048, 5)}
+SCRATCH_FLOATS = 1 << 28  # 1 GiB read before each cold transform
+
+
+def _frac(nbytes, ms):
+    return round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if ms and ms > 0 else None
+
+
+def time_passes(F, torch, plan, batch, rows, cols, x, y, iters, scratch):
+    """Per pass of a two-pass plan, the mean kernel duration (HIP events bound
+    to each launch) of the pass itself ("fft"), of the same kernel with its
+    arithmetic switched off ("no_arith": loads, LDS exchanges, stores) and with
+    its arithmetic and exchanges switched off ("copy": a copy with the pass's
+    access pattern), each transform preceded by a 1 GiB read (no input in the
+    MALL, nothing dirty there), passes back to back as in fft2d_exec. The
+    fraction of the copy is copy / fft: 1.0 means the pass runs at the speed
+    of its own data movement."""
+    stream = torch.cuda.current_stream()
+    sh = int(stream.cuda_stream)
+    passes = [p for p, n in ((0, cols), (1, rows)) if n > 1]
+    nbytes = BYTES_PER_POINT_PER_PASS * batch * rows * cols
+    xp, yp = x.data_ptr(), y.data_ptr()
+    out = {}
+    for variant, mode in (("fft", 0), ("no_arith", F.ABLATE_ARITHMETIC), ("copy", F.ABLATE_EXCHANGE)):
+        ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in passes]
+              for _ in range(iters + 2)]
+        for row in ev:
+            for a, b in row:
+                a.record(stream)
+                b.record(stream)
+        torch.cuda.synchronize()
+        try:
+            for row in ev:
+                scratch.sum()
+                for pidx, (a, b) in zip(passes, row):
+                    if mode == 0:
+                        F.fft2d_exec_pass_timed(plan.handle, xp, yp, F.FORWARD, pidx, a.cuda_event, b.cuda_event, sh)
+                    else:
+                        F.fft2d_exec_pass_ablated(plan.handle, xp, yp, pidx, mode, a.cuda_event, b.cuda_event, sh)
+        except F.Fft2dError:  # no measurement variant compiled for this plan's kernels
+            torch.cuda.synchronize()
+            continue
+        torch.cuda.synchronize()
+        for i, pidx in enumerate(passes):
+            t = float(np.mean([row[i][0].elapsed_time(row[i][1]) for row in ev[2:]]))
+            out.setdefault("row" if pidx == 0 else "col", {})[variant + "_ms"] = round(t, 5)
+    for name, e in out.items():
+        e["frac"] = _frac(nbytes, e.get("fft_ms"))
+        if "copy_ms" in e:
+            e["copy_frac"] = _frac(nbytes, e["copy_ms"])
+            e["fft_over_copy"] = round(e["fft_ms"] / e["copy_ms"], 3)
+        if "no_arith_ms" in e:
+            e["fft_over_no_arith"] = round(e["fft_ms"] / e["no_arith_ms"], 3)
+    return out
 
 
 def time_configs(F, torch, iters):
@@ -230,11 +364,12 @@ def time_configs(F, torch, iters):
     events, so the 256 MB MALL holds none of the input, but holds dirty lines
     of the scratch that are written back while the transform runs) and
     cold_clean (the scratch is read instead: no input in the MALL and nothing
-    to write back): median, mean, min."""
+    to write back): median, mean, min; and for two-pass plans each pass,
+    cold_clean, against its data-movement floors (time_passes)."""
     import synth
     stream = torch.cuda.current_stream()
     sh = int(stream.cuda_stream)
-    scratch = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+    scratch = torch.empty(SCRATCH_FLOATS, dtype=torch.float32, device="cuda")
     res = {}
     for name, batch, rows, cols, seed in CONFIGS:
         shape = (batch, rows, cols) if batch > 1 else (rows, cols)
@@ -244,7 +379,8 @@ def time_configs(F, torch, iters):
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(iters)]
         out = {}
         # HBM passes: a length-1 dimension needs none; a whole-grid plan reads and writes once
-        npass = 1 if " grid[" in plan.describe() else int(rows > 1) + int(cols > 1)
+        whole = " grid[" in plan.describe()
+        npass = 1 if whole else int(rows > 1) + int(cols > 1)
         for mode in ("warm", "cold", "cold_clean"):
             for _ in range(3):
                 F.fft2d_exec(plan.handle, x.data_ptr(), y.data_ptr(), F.FORWARD, sh)
@@ -263,7 +399,10 @@ def time_configs(F, torch, iters):
             out[mode] = {"median_ms": round(med, 5), "mean_ms": round(float(t.mean()), 5),
                          "min_ms": round(float(t.min()), 5),
                          "gflops": round(flops_2d(rows, cols, batch) / med / 1e6, 1),
-                         "hbm_gbps": round(npass * BYTES_PER_POINT_PER_PASS * pts / med / 1e6, 1)}
+                         "hbm_gbps": round(npass * BYTES_PER_POINT_PER_PASS * pts / med / 1e6, 1),
+                         "frac": _frac(npass * BYTES_PER_POINT_PER_PASS * pts, med)}
+        if not whole:
+            out["passes_cold_clean"] = time_passes(F, torch, plan, batch, rows, cols, x, y, iters, scratch)
         out["plan"] = plan.describe()
         res[name] = out
         del x, y
@@ -272,28 +411,77 @@ def time_configs(F, torch, iters):
     return res
 
 
-def device_copy_gbps(torch, rows, cols, iters=20):
-    """Read+write bandwidth of a plain device copy of one rows x cols complex64
-    grid (torch's copy kernel), warm (source and destination stay in the 256 MB
-    MALL) and cold (1 GiB scrubbed before each copy)."""
-    x = torch.zeros((rows, cols), dtype=torch.complex64, device="cuda")
+def only_config(F, torch, name, steps, warmup):
+    """One configuration's forward transform, `warmup` + `steps` times back to
+    back (for rocprofv3: its kernel statistics then hold that configuration's
+    passes only), then `steps` times pass by pass with events bound to each
+    launch; prints one JSON line with the per-pass mean durations."""
+    import synth
+    batch, rows, cols, seed = ONLY[name]
+    shape = (batch, rows, cols) if batch > 1 else (rows, cols)
+    x = torch.from_numpy(synth.complex_grid(seed, shape)).to("cuda")
     y = torch.empty_like(x)
-    scratch = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+    plan = F.get_plan(batch, rows, cols, x.device)
     stream = torch.cuda.current_stream()
-    out = {}
-    for mode in ("warm", "cold"):
+    sh = int(stream.cuda_stream)
+    for _ in range(warmup):
+        F.fft2d_exec(plan.handle, x.data_ptr(), y.data_ptr(), F.FORWARD, sh)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        F.fft2d_exec(plan.handle, x.data_ptr(), y.data_ptr(), F.FORWARD, sh)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps * 1e3
+    whole = " grid[" in plan.describe()
+    passes = [] if whole else [p for p, n in ((0, cols), (1, rows)) if n > 1]
+    ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in passes]
+          for _ in range(steps)]
+    for row in ev:
+        for a, b in row:
+            a.record(stream)
+            b.record(stream)
+    torch.cuda.synchronize()
+    for row in ev:
+        for pidx, (a, b) in zip(passes, row):
+            F.fft2d_exec_pass_timed(plan.handle, x.data_ptr(), y.data_ptr(), F.FORWARD, pidx, a.cuda_event,
+                                    b.cuda_event, sh)
+    torch.cuda.synchronize()
+    nbytes = BYTES_PER_POINT_PER_PASS * batch * rows * cols
+    per = {}
+    for i, pidx in enumerate(passes):
+        t = float(np.mean([row[i][0].elapsed_time(row[i][1]) for row in ev]))
+        per["row" if pidx == 0 else "col"] = {"ms": round(t, 5), "frac": _frac(nbytes, t)}
+    print(json.dumps({"only": name, "steps": steps, "warmup": warmup, "ms_per_transform": round(wall, 5),
+                      "passes": per, "plan": plan.describe()}), flush=True)
+
+
+def device_copy_gbps(torch, iters=20):
+    """Read+write bandwidth of a plain device copy (torch's copy_ of a
+    contiguous tensor, which runs the HIP runtime's copy kernel), 512 MiB to
+    512 MiB (1 GiB of traffic): warm (back to back), and cold_clean (a
+    different 1 GiB buffer read before each copy, so neither source nor
+    destination sits in the MALL and nothing dirty is left there)."""
+    n = 1 << 26  # complex64 points: 512 MiB
+    x = torch.zeros(n, dtype=torch.complex64, device="cuda")
+    y = torch.empty_like(x)
+    scratch = torch.empty(SCRATCH_FLOATS, dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+    out = {"bytes_per_copy": 2 * n * 8}
+    for mode in ("warm", "cold_clean"):
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(iters)]
         for _ in range(3):
             y.copy_(x)
         for a, b in ev:
-            if mode == "cold":
-                scratch.zero_()
+            if mode == "cold_clean":
+                scratch.sum()
             a.record(stream)
             y.copy_(x)
             b.record(stream)
         torch.cuda.synchronize()
         med = float(np.median([a.elapsed_time(b) for a, b in ev]))
-        out[mode + "_gbps"] = round(2 * x.numel() * 8 / med / 1e6, 1)
+        out[mode + "_ms"] = round(med, 5)
+        out[mode + "_gbps"] = round(2 * n * 8 / med / 1e6, 1)
+        out[mode + "_frac"] = _frac(2 * n * 8, med)
     del x, y, scratch
     torch.cuda.empty_cache()
     return out
@@ -470,6 +658,18 @@ def time_batched(F, torch, steps, warmup, seed):
     return res
 
 
+def cpu_model():
+    """The host CPU's model name (/proc/cpuinfo), or None."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(rows, cols, x, budget_s, max_reps, threads=0):
     """The FP64 oracle (plain recursive radix-2, OpenMP) on the same input;
     threads = 0 uses every host core."""
@@ -486,7 +686,7 @@ def cpu_baseline(rows, cols, x, budget_s, max_reps, threads=0):
             break
     dt = time.perf_counter() - t0
     gflops = 2 * flops_2d(rows, cols) * reps / dt / 1e9
-    return ref, {"value": gflops, "unit": "GFLOP/s", "cores": used, "kind": "oracle",
+    return ref, {"value": gflops, "unit": "GFLOP/s", "cores": used, "kind": "oracle", "cpu_model": cpu_model(),
                  "sample": "%d forward+inverse round trips of the %dx%d grid, FP64 recursive radix-2 with OpenMP "
                            "over rows then columns, %.1f s" % (reps, rows, cols, dt)}
 
@@ -504,15 +704,24 @@ BATCHED_SEED = 4
 BATCHED_COUNT = 512
 
 
+BACKWARD_CASE = ("8 x 2048x2048 backward (adjoint)", (8, 2048, 2048), 5)
+
+
 def gpu_forward_outputs(F, torch):
-    """The library's forward transform of every ORACLE_CASES input and of the
-    512-shape batched set (one batched launch), copied to the host."""
+    """The library's forward transform of every ORACLE_CASES input, its
+    adjoint (fft2d_backward of the forward transform) of the BACKWARD_CASE
+    input, and the forward transforms of the 512-shape batched set (one
+    batched launch), copied to the host."""
     import synth
     out = {}
     for name, shape, seed in ORACLE_CASES:
         x = torch.from_numpy(synth.complex_grid(seed, shape)).to("cuda")
         out[name] = F.fft2(x).cpu().numpy()
         del x
+    name, shape, seed = BACKWARD_CASE
+    x = torch.from_numpy(synth.complex_grid(seed, shape)).to("cuda")
+    out[name] = F.get_plan(shape[0], shape[1], shape[2], x.device).backward(x, F.FORWARD).cpu().numpy()
+    del x
     xs = [torch.from_numpy(g).to("cuda")
           for g in synth.batched_grids(BATCHED_SEED, synth.pow2_shapes(BATCHED_SEED, BATCHED_COUNT))]
     out["batched"] = [y.cpu().numpy() for y in F.fft2_batched(xs)]
@@ -521,35 +730,48 @@ def gpu_forward_outputs(F, torch):
     return out
 
 
+def errors(got, ref):
+    """(relative L2, largest element error over the reference's RMS magnitude), in FP64."""
+    d = np.abs(got.astype(np.complex128) - ref).ravel()
+    den = float(np.linalg.norm(ref.ravel()))
+    rms = den / math.sqrt(ref.size)
+    return float(np.linalg.norm(d)) / den, float(d.max()) / rms
+
+
 def rel_l2(got, ref):
-    return float(np.linalg.norm((got.astype(np.complex128) - ref).ravel()) / np.linalg.norm(ref.ravel()))
+    return errors(got, ref)[0]
 
 
 def cpu_configs(gpu_out, threads=0):
-    """The FP64 oracle's forward transform of each configuration once (all host
-    cores), for GPU/CPU context beside the 4096^2 baseline, and the relative L2
-    error of the library's result for the same input against it."""
+    """The FP64 oracle's transform of each configuration once (all host
+    cores), for GPU/CPU context beside the 4096^2 baseline, and the error of
+    the library's result for the same input against it: relative L2 and the
+    largest element error over the reference's RMS magnitude (the GPU tests'
+    two bounds, 1e-5 each). The backward case checks fft2d_backward against
+    the oracle's adjoint."""
     import oracle
     import synth
     out = {}
-    for name, shape, seed in ORACLE_CASES:
+    for name, shape, seed in ORACLE_CASES + [BACKWARD_CASE]:
         x = synth.complex_grid(seed, shape)
         t0 = time.perf_counter()
-        ref = oracle.fft2_forward(x, threads)
+        ref = oracle.adjoint(x, oracle.FORWARD, threads) if name == BACKWARD_CASE[0] else oracle.fft2_forward(x, threads)
         dt = time.perf_counter() - t0
         batch = int(np.prod(shape[:-2])) if len(shape) > 2 else 1
+        rel, mx = errors(gpu_out[name], ref)
         out[name] = {"seconds": round(dt, 4), "gflops": round(flops_2d(shape[-2], shape[-1], batch) / dt / 1e9, 2),
-                     "gpu_rel_l2": rel_l2(gpu_out[name], ref)}
+                     "gpu_rel_l2": rel, "gpu_max_elem": mx}
         del x, ref
     shapes = synth.pow2_shapes(BATCHED_SEED, BATCHED_COUNT)
     xs = synth.batched_grids(BATCHED_SEED, shapes)
     t0 = time.perf_counter()
     refs = [oracle.fft2_forward(x, threads) for x in xs]
     dt = time.perf_counter() - t0
-    errs = [rel_l2(g, r) for g, r in zip(gpu_out["batched"], refs)]
+    errs = [errors(g, r) for g, r in zip(gpu_out["batched"], refs)]
     out["%d shapes 2^a x 2^b forward" % BATCHED_COUNT] = {"seconds": round(dt, 4),
                                            "gflops": round(sum(flops_2d(r, c) for r, c in shapes) / dt / 1e9, 2),
-                                           "gpu_rel_l2_max": max(errs)}
+                                           "gpu_rel_l2_max": max(e[0] for e in errs),
+                                           "gpu_max_elem_max": max(e[1] for e in errs)}
     return out
 
 
@@ -564,18 +786,27 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the backward and batched comparisons")
     ap.add_argument("--copy-only", action="store_true",
                     help="only run plain device copies of the 4096x4096 grid (calibrates rocprofv3 byte counters)")
+    ap.add_argument("--only", choices=sorted(ONLY),
+                    help="run only this configuration's forward transform (warmup + steps back to back, then "
+                         "steps pass by pass with bound events) and print its per-pass times")
+    ap.add_argument("--vendor-context", action="store_true",
+                    help="also time torch.fft.fft2 (ROCm's FFT library) on the large configurations, for context")
     ap.add_argument("--summarize-traffic", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
                     help="print HBM bytes per pass from four rocprofv3 --pmc output folders, then exit")
     ap.add_argument("--summarize-counters", nargs="+", metavar="DIR",
                     help="print the mean of every counter per pass from rocprofv3 --pmc output folders, then exit")
     ap.add_argument("--summarize-stats", metavar="DIR",
                     help="print the kernel rows of a rocprofv3 --kernel-trace --stats output folder, then exit")
+    ap.add_argument("--profiled", default="4096x4096",
+                    help="for --summarize-*: the workload profiled: 4096x4096 (the round trip) or an --only name")
     args = ap.parse_args()
+    roles = ROUND_TRIP_ROLES if args.profiled == "4096x4096" else FORWARD_ROLES
     if args.summarize_traffic:
-        print(summarize_traffic(*args.summarize_traffic))
+        b, r_, c_, _ = ONLY[args.profiled]
+        print(summarize_traffic(*args.summarize_traffic, points=b * r_ * c_, roles=roles))
         return
     if args.summarize_counters:
-        print(summarize_counters(*args.summarize_counters))
+        print(summarize_counters(*args.summarize_counters, roles=roles))
         return
     if args.summarize_stats:
         print(summarize_stats(args.summarize_stats))
@@ -602,6 +833,9 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
         print(json.dumps({"copy_only": True, "bytes_per_copy": 2 * x.numel() * 8, "copies": args.warmup + args.steps}))
+        return
+    if args.only:
+        only_config(F, torch, args.only, args.steps, args.warmup)
         return
     log("bench: %dx%d forward+inverse, steps=%d warmup=%d" % (rows, cols, args.steps, args.warmup))
     r = time_plain(F, torch, rows, cols, args.steps, args.warmup, args.seed)
@@ -636,6 +870,7 @@ def main():
         "roofline": {"bound": "hbm", "kernel": pass_names[dom] + " pass", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(pass_names[dom])},
+        "roofline_rocprof": rocprof_roofline(pass_names[dom], pass_bytes),
         "per_pass_ms": {n: round(float(v), 5) for n, v in zip(pass_names, mean_pass)},
         "per_pass_gbps": {n: round(pass_bytes / (float(v) * 1e-3) / 1e9, 1) for n, v in zip(pass_names, mean_pass)},
         "roundtrip_rel_l2": r["roundtrip_rel_l2"],
@@ -658,14 +893,19 @@ def main():
             "cold_clean_ms": one["cold_clean"]["median_ms"],
             "frac_cold_clean": round(alg / (one["cold_clean"]["median_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "frac_warm": round(alg / (one["warm"]["median_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
-        log("bench: device copy bandwidth, 4096 x 4096 complex64")
-        result["device_copy"] = device_copy_gbps(torch, rows, cols)
+        passes = one.get("passes_cold_clean", {})
+        if "row" in passes and "copy_ms" in passes["row"]:
+            # the dominant kernel (the forward row pass) against a copy with its own access pattern
+            result["roofline"]["frac_of_same_pattern_copy"] = round(passes["row"]["copy_ms"] / passes["row"]["fft_ms"], 4)
+        log("bench: device copy bandwidth, 512 MiB to 512 MiB")
+        result["device_copy"] = device_copy_gbps(torch)
         log("bench: energy per transform (1024 x 1024 and 4096 x 4096)")
         result["energy"] = [energy(F, torch, 1024, 1024, 1.5), energy(F, torch, 4096, 4096, 1.5)]
         log("bench: batched 512 shapes vs 512 plain launches")
         result["batched_vs_plain"] = time_batched(F, torch, 10, 3, 4)
-        log("bench: torch.fft.fft2 (vendor FFT) on the same inputs, context")
-        result["vendor_fft_context"] = vendor_fft_context(F, torch)
+        if args.vendor_context:
+            log("bench: torch.fft.fft2 (vendor FFT) on the same inputs, context")
+            result["vendor_fft_context"] = vendor_fft_context(F, torch)
 
     if not args.no_cpu:
         log("bench: CPU baseline (FP64 oracle)")
@@ -677,8 +917,9 @@ def main():
         if not args.no_extras:
             log("bench: FP64 oracle on the other configurations (context, and the library's error on each)")
             result["cpu_oracle_configs"] = cpu_configs(gpu_forward_outputs(F, torch))
-        num = np.linalg.norm((r["y"].astype(np.complex128) - ref).ravel())
-        result["fwd_rel_l2_vs_oracle"] = float(num / np.linalg.norm(ref.ravel()))
+        rel, mx = errors(r["y"], ref)
+        result["fwd_rel_l2_vs_oracle"] = rel
+        result["fwd_max_elem_vs_oracle"] = mx
 
     print(json.dumps(result), flush=True)
 

@@ -215,6 +215,34 @@ fft2d_status fft2d_exec_pass(fft2d_plan_t plan, const void* in, void* out, int d
 fft2d_status fft2d_exec_pass_timed(fft2d_plan_t plan, const void* in, void* out, int direction, int pass,
                                    void* start_event, void* stop_event, void* stream);
 
+/* Ablations of fft2d_exec_pass_ablated. */
+#define FFT2D_ABLATE_ARITHMETIC 1 /* loads, LDS exchanges and stores; no twiddles, no butterflies */
+#define FFT2D_ABLATE_EXCHANGE 2   /* loads and stores only: a copy with the pass's access pattern */
+
+/*
+ * fft2d_exec_pass_ablated -- a measurement aid: one pass of a uniform plan
+ * with part of its work switched off, the way the paper's Table 2 times its
+ * FFT with single components (compute, reorderings, transfers) disabled
+ * (Section 4). The pass keeps its kernel's workgroups, tiles, load and store
+ * instructions, addresses and cache policies; with FFT2D_ABLATE_ARITHMETIC it
+ * also keeps the LDS exchanges (the on-chip reorderings) but drops the
+ * twiddle loads, multiplications and butterflies; with FFT2D_ABLATE_EXCHANGE
+ * it drops the exchanges too and each thread stores the points it loaded.
+ * Its duration is therefore the data-movement floor of that pass. The output
+ * is a reordered copy of the input, not a transform.
+ *   pass        : 0 (row pass) or 1 (column pass), as for fft2d_exec_pass;
+ *                 in, out and the intermediate buffer as there.
+ *   ablation    : FFT2D_ABLATE_ARITHMETIC or FFT2D_ABLATE_EXCHANGE
+ *                 (else FFT2D_ERR_INVALID_DIRECTION).
+ *   start_event, stop_event : both null, or hipEvent_t handles bound to the
+ *                 launch as in fft2d_exec_pass_timed.
+ * Only the pass kernels of the benchmarked grids carry these variants
+ * (4096 x 4096, 8192 x 8192, 16384 x 2048, 8 x 2048 x 2048, 1024 x 1024,
+ * batches of 16384-point rows): another pass returns FFT2D_ERR_INVALID_SIZE.
+ */
+fft2d_status fft2d_exec_pass_ablated(fft2d_plan_t plan, const void* in, void* out, int pass, int ablation,
+                                     void* start_event, void* stop_event, void* stream);
+
 /* fft2d_destroy -- free a plan and its device memory. NULL is a no-op. Waits for
  * no stream: the caller must make sure no enqueued work still uses the plan. */
 fft2d_status fft2d_destroy(fft2d_plan_t plan);

@@ -41,6 +41,7 @@ STATUS_NAMES = {
 
 # Every symbol the public header declares.
 EXPORTS = ("fft2d_plan", "fft2d_plan_batched", "fft2d_exec", "fft2d_exec_pass", "fft2d_exec_pass_timed",
+           "fft2d_exec_pass_ablated",
            "fft2d_exec_batched",
            "fft2d_backward", "fft2d_destroy", "fft2d_status_string", "fft2d_last_error", "fft2d_plan_describe",
            "fft2d_plan_twiddles", "fft2d_exec_noalloc", "fft2d_version")
@@ -67,6 +68,7 @@ def _load():
     lib.fft2d_exec.argtypes = [vp, vp, vp, ci, vp]
     lib.fft2d_exec_pass.argtypes = [vp, vp, vp, ci, ci, vp]
     lib.fft2d_exec_pass_timed.argtypes = [vp, vp, vp, ci, ci, vp, vp, vp]
+    lib.fft2d_exec_pass_ablated.argtypes = [vp, vp, vp, ci, ci, vp, vp, vp]
     lib.fft2d_exec_batched.argtypes = [vp, vp, vp, ci, vp]
     lib.fft2d_backward.argtypes = [vp, vp, vp, ci, vp]
     lib.fft2d_destroy.argtypes = [vp]
@@ -80,6 +82,7 @@ def _load():
     lib.fft2d_version.argtypes = []
     lib.fft2d_version.restype = ci
     for f in ("fft2d_plan", "fft2d_plan_batched", "fft2d_exec", "fft2d_exec_pass", "fft2d_exec_pass_timed",
+              "fft2d_exec_pass_ablated",
               "fft2d_exec_batched", "fft2d_backward",
               "fft2d_destroy", "fft2d_plan_describe", "fft2d_plan_twiddles", "fft2d_exec_noalloc"):
         getattr(lib, f).restype = ci
@@ -139,6 +142,19 @@ def fft2d_exec_pass_timed(plan: int, in_ptr: int, out_ptr: int, direction: int, 
     once the event has been recorded); they take the pass kernel's own start and end times."""
     _check(lib.fft2d_exec_pass_timed(plan, in_ptr, out_ptr, int(direction), int(pass_index), start_event,
                                      stop_event, stream), "fft2d_exec_pass_timed")
+
+
+ABLATE_ARITHMETIC = 1
+ABLATE_EXCHANGE = 2
+
+
+def fft2d_exec_pass_ablated(plan: int, in_ptr: int, out_ptr: int, pass_index: int, ablation: int,
+                            start_event: int = 0, stop_event: int = 0, stream: int = 0) -> None:
+    """One pass with its arithmetic (ABLATE_ARITHMETIC) or its arithmetic and LDS exchanges
+    (ABLATE_EXCHANGE) switched off: the pass's data-movement floor. Events as for
+    fft2d_exec_pass_timed, or both 0."""
+    _check(lib.fft2d_exec_pass_ablated(plan, in_ptr, out_ptr, int(pass_index), int(ablation),
+                                       start_event or None, stop_event or None, stream), "fft2d_exec_pass_ablated")
 
 
 def pointer_array(ptrs):

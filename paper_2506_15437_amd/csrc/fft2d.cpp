@@ -203,12 +203,27 @@ hipError_t upload_root_table(int64_t n, float2** dev) {
   return e;
 }
 
+// Launch one pass kernel: the pass itself, or with probe = 1 or 2 its
+// measurement variant (see PassKernel::launch_probe).
+fft2d_status launch_one(const PassKernel* k, const PassArgs& a, int sign, hipStream_t s, hipEvent_t t0,
+                        hipEvent_t t1, int probe, const char* what) {
+  hipError_t e;
+  if (probe) {
+    if (!k->launch_probe) return fail(FFT2D_ERR_INVALID_SIZE, std::string("no measurement variant of the ") + what);
+    e = k->launch_probe(a, probe, s, t0, t1);
+  } else {
+    e = k->launch(a, sign, s, t0, t1);
+  }
+  return e == hipSuccess ? FFT2D_OK : hip_fail(e, what);
+}
+
 // Enqueue the transform of nb consecutive grids of rows x cols (in, out and
 // work point at the first of them): the whole-grid kernel, or the row pass then
 // the column pass (only_pass = 0 or 1 restricts it to one of them; t0, t1:
-// timing events bound to that pass's launch, or null).
+// timing events bound to that pass's launch, or null; probe: 0, or the
+// measurement variant of the pass, with only_pass 0 or 1).
 fft2d_status run_grids(const fft2d_plan_s* p, int64_t nb, const float2* in, float2* out, float2* work, int sign,
-                       float scale, hipStream_t s, int only_pass, hipEvent_t t0, hipEvent_t t1) {
+                       float scale, hipStream_t s, int only_pass, hipEvent_t t0, hipEvent_t t1, int probe) {
   const int64_t npts = nb * p->rows * p->cols;
   hipError_t e;
   if (!p->row_k && !p->col_k) {
@@ -248,8 +263,8 @@ fft2d_status run_grids(const fft2d_plan_s* p, int64_t nb, const float2* in, floa
       a.m2 = p->m2;
       a.scale = 1.0f;
       a.nblocks = (int)(nb * p->m2);
-      e = p->row_k->launch(a, sign, s, t0, t1);
-      if (e != hipSuccess) return hip_fail(e, "row pass (combine) launch");
+      const fft2d_status st = launch_one(p->row_k, a, sign, s, t0, t1, probe, "row pass (combine) launch");
+      if (st != FFT2D_OK) return st;
     }
     if (only_pass != 0) {
       PassArgs a{};
@@ -264,8 +279,8 @@ fft2d_status run_grids(const fft2d_plan_s* p, int64_t nb, const float2* in, floa
       a.m2 = p->m2;
       a.scale = scale;
       a.nblocks = pass_blocks(*p->col_k, a.nvec);
-      e = p->col_k->launch(a, sign, s, t0, t1);
-      if (e != hipSuccess) return hip_fail(e, "column pass launch");
+      const fft2d_status st = launch_one(p->col_k, a, sign, s, t0, t1, probe, "column pass launch");
+      if (st != FFT2D_OK) return st;
     }
     return FFT2D_OK;
   }
@@ -282,8 +297,9 @@ fft2d_status run_grids(const fft2d_plan_s* p, int64_t nb, const float2* in, floa
     a.m1 = 1;
     a.scale = p->col_k ? 1.0f : scale;
     a.nblocks = pass_blocks(*p->row_k, a.nvec);
-    e = p->row_k->launch(a, sign, s, only_pass == 0 ? t0 : nullptr, only_pass == 0 ? t1 : nullptr);
-    if (e != hipSuccess) return hip_fail(e, "row pass launch");
+    const fft2d_status st = launch_one(p->row_k, a, sign, s, only_pass == 0 ? t0 : nullptr,
+                                      only_pass == 0 ? t1 : nullptr, probe, "row pass launch");
+    if (st != FFT2D_OK) return st;
     src = out;
   }
   if (p->col_k && only_pass != 0) {
@@ -298,8 +314,9 @@ fft2d_status run_grids(const fft2d_plan_s* p, int64_t nb, const float2* in, floa
     a.m1 = 1;
     a.scale = scale;
     a.nblocks = pass_blocks(*p->col_k, a.nvec);
-    e = p->col_k->launch(a, sign, s, only_pass == 1 ? t0 : nullptr, only_pass == 1 ? t1 : nullptr);
-    if (e != hipSuccess) return hip_fail(e, "column pass launch");
+    const fft2d_status st = launch_one(p->col_k, a, sign, s, only_pass == 1 ? t0 : nullptr,
+                                      only_pass == 1 ? t1 : nullptr, probe, "column pass launch");
+    if (st != FFT2D_OK) return st;
   }
   return FFT2D_OK;
 }
@@ -311,14 +328,16 @@ constexpr int64_t kMaxLaunchPoints = int64_t(1) << 31;
 
 // Enqueue the transform of the plan's whole batch.
 fft2d_status run_uniform(const fft2d_plan_s* p, const float2* in, float2* out, int sign, float scale,
-                         hipStream_t s, int only_pass = -1, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr) {
+                         hipStream_t s, int only_pass = -1, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr,
+                         int probe = 0) {
   const int64_t per = p->rows * p->cols;
   const int64_t chunk = std::max<int64_t>(1, kMaxLaunchPoints / per);
   for (int64_t b0 = 0; b0 < p->batch; b0 += chunk) {
     const int64_t nb = std::min(chunk, p->batch - b0);
     const int64_t off = b0 * per;
     const fft2d_status st =
-        run_grids(p, nb, in + off, out + off, p->work ? p->work + off : nullptr, sign, scale, s, only_pass, t0, t1);
+        run_grids(p, nb, in + off, out + off, p->work ? p->work + off : nullptr, sign, scale, s, only_pass, t0, t1,
+                  probe);
     if (st != FFT2D_OK) return st;
   }
   return FFT2D_OK;
@@ -605,7 +624,7 @@ namespace {
 
 // Shared by fft2d_exec_pass and fft2d_exec_pass_timed.
 fft2d_status exec_one_pass(fft2d_plan_t plan, const void* in, void* out, int direction, int pass, void* stream,
-                           hipEvent_t t0, hipEvent_t t1, const char* name) {
+                           hipEvent_t t0, hipEvent_t t1, const char* name, int probe = 0) {
   if (!plan) return fail(FFT2D_ERR_NULL_POINTER, "plan is NULL");
   if (!is_live(plan)) return fail(FFT2D_ERR_INVALID_PLAN, "plan handle is not live");
   if (plan->kind != kUniform) return fail(FFT2D_ERR_WRONG_PLAN_KIND, std::string("batched plan passed to ") + name);
@@ -622,7 +641,8 @@ fft2d_status exec_one_pass(fft2d_plan_t plan, const void* in, void* out, int dir
   fft2d_status st = check_data_ptrs(in, out, bytes);
   if (st != FFT2D_OK) return st;
   const float scale = direction == FFT2D_INVERSE ? (float)(1.0 / (double)per) : 1.0f;
-  return run_uniform(plan, (const float2*)in, (float2*)out, direction, scale, (hipStream_t)stream, pass, t0, t1);
+  return run_uniform(plan, (const float2*)in, (float2*)out, direction, scale, (hipStream_t)stream, pass, t0, t1,
+                     probe);
 }
 
 }  // namespace
@@ -636,6 +656,16 @@ fft2d_status fft2d_exec_pass_timed(fft2d_plan_t plan, const void* in, void* out,
   if (!start_event || !stop_event) return fail(FFT2D_ERR_NULL_POINTER, "start_event and stop_event must be events");
   return exec_one_pass(plan, in, out, direction, pass, stream, (hipEvent_t)start_event, (hipEvent_t)stop_event,
                        "fft2d_exec_pass_timed");
+}
+
+fft2d_status fft2d_exec_pass_ablated(fft2d_plan_t plan, const void* in, void* out, int pass, int ablation,
+                                    void* start_event, void* stop_event, void* stream) {
+  if (ablation != FFT2D_ABLATE_ARITHMETIC && ablation != FFT2D_ABLATE_EXCHANGE)
+    return fail(FFT2D_ERR_INVALID_DIRECTION, "ablation must be FFT2D_ABLATE_ARITHMETIC or FFT2D_ABLATE_EXCHANGE");
+  if ((start_event == nullptr) != (stop_event == nullptr))
+    return fail(FFT2D_ERR_NULL_POINTER, "give both timing events or neither");
+  return exec_one_pass(plan, in, out, FFT2D_FORWARD, pass, stream, (hipEvent_t)start_event, (hipEvent_t)stop_event,
+                       "fft2d_exec_pass_ablated", ablation);
 }
 
 fft2d_status fft2d_exec_batched(fft2d_plan_t plan, const void* const* in, void* const* out, int direction,

@@ -55,6 +55,9 @@ struct PassKernel {
   int radix[kMaxPasses];
   size_t lds_bytes;
   hipError_t (*launch)(const PassArgs&, int dir, hipStream_t, hipEvent_t t0, hipEvent_t t1);
+  // Measurement variants (mode 1: loads, LDS exchanges and stores without
+  // arithmetic; mode 2: loads and stores only); null where not compiled.
+  hipError_t (*launch_probe)(const PassArgs&, int mode, hipStream_t, hipEvent_t t0, hipEvent_t t1);
 };
 
 // One compiled whole-grid kernel: the 2D transform of `rows` x `cols` grids,

@@ -1,5 +1,7 @@
 // Kernel tables of split column transforms: row passes with an M1-point combine and the
-// column passes of length rows/M1.
+// column passes of length rows/M1. The kernels of the benchmarked grids (4096^2,
+// 8192^2, 16384 x 2048, 8 x 2048^2) also carry their measurement variants
+// (describe's PROBE flag).
 #include "fft_pass.hpp"
 #include "fft_tables.h"
 
@@ -26,13 +28,13 @@ using S2048 = Cfg<2048, 32, 16, 2, true, 16, 16, 8>;
 using S4096 = Cfg<4096, 32, 8, 2, true, 16, 16, 16>;
 
 const PassKernel kCombineKernels[] = {
-    describe<RC8192x2, true, 4>(), describe<RC8192x4, true, 1>(), describe<RC16384x2, true, 1>(),
-    describe<RC4096x4, true, 4>(),
-    describe<RC2048x8, true, 4>(),
+    describe<RC8192x2, true, 4>(), describe<RC8192x4, true, 1, true, true>(), describe<RC16384x2, true, 1>(),
+    describe<RC4096x4, true, 4, true, true>(),
+    describe<RC2048x8, true, 4, true, true>(),
     describe<RC1024x16, true, 4>(),
 };
 const PassKernel kSplitColKernels[] = {
-    describe<S512>(), describe<S1024>(), describe<S2048>(), describe<S4096>(),
+    describe<S512>(), describe<S1024, false, 1, false, true>(), describe<S2048>(), describe<S4096>(),
 };
 // Column passes with 64 points per thread (512 threads) for split transforms
 // whose data come from HBM rather than the MALL (large grids): more loads in
@@ -41,7 +43,7 @@ using S2048W = Cfg<2048, 64, 16, 2, true, 16, 16, 8>;
 using S4096W = Cfg<4096, 64, 8, 4, true, 16, 16, 16>;
 using S8192W = Cfg<8192, 64, 4, 2, true, 16, 16, 32>;
 const PassKernel kSplitColWideKernels[] = {
-    describe<S2048W>(), describe<S4096W>(), describe<S8192W>(),
+    describe<S2048W, false, 1, false, true>(), describe<S4096W>(), describe<S8192W>(),
 };
 
 }  // namespace

@@ -294,7 +294,11 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
 
 // One pass: butterflies of this thread, then (unless last) the LDS exchange.
 // `tw` covers this pass kernel's twiddle table.
-template <class K, int DIR, int p, int SB = 0>
+// ARITH = false keeps the data movement of the pass (the LDS exchange in the
+// same order) and drops its arithmetic (twiddle loads, multiplications and the
+// butterflies): the "compute off" variant used to measure the pass's
+// data-movement ceiling.
+template <class K, int DIR, int p, int SB = 0, bool ARITH = true>
 __device__ __forceinline__ void run_pass(float2 (&d)[K::E], float2* lds, int tt, int c, const Buf& tw) {
   constexpr int R = K::radix(p);
   constexpr int Ns = K::ns(p);
@@ -309,7 +313,7 @@ __device__ __forceinline__ void run_pass(float2 (&d)[K::E], float2* lds, int tt,
       constexpr int r = decltype(Rr)::value;
       x[r] = d[i + NB * r];
     });
-    if constexpr (p > 0) {
+    if constexpr (p > 0 && ARITH) {
       const uint32_t voff = (uint32_t)(b & (Ns - 1)) * 8u;
       static_for<1, R>([&](auto Rr) {
         constexpr int r = decltype(Rr)::value;
@@ -318,7 +322,7 @@ __device__ __forceinline__ void run_pass(float2 (&d)[K::E], float2* lds, int tt,
         x[r] = cmul(x[r], w);
       });
     }
-    dft<R, DIR>(x);
+    if constexpr (ARITH) dft<R, DIR>(x);
     static_for<0, R>([&](auto S) {
       constexpr int s = decltype(S)::value;
       if constexpr (last) d[i + NB * s] = x[s];
@@ -378,7 +382,11 @@ struct TileIO {
 // the tile's first point, so every lane needs one 32-bit offset register and
 // the E points differ by uniform offsets.
 // AUX: cache policy of the input loads (0, kAuxNontemporal, or kAuxDevice).
-template <class K, int DIR, int AUX = 0, int SB = 0>
+// MODE: 0 the FFT; 1 its data movement only (loads, LDS exchanges, stores;
+// no arithmetic); 2 loads and stores only (a copy with the tile's access
+// pattern). Modes 1 and 2 are measurement variants (the paper's Table 2
+// times its FFT with components switched off in the same way).
+template <class K, int DIR, int AUX = 0, int SB = 0, int MODE = 0>
 __device__ __forceinline__ void fft_tile(const PassArgs& a, int w, float2* lds, TileIO io) {
   const int t = threadIdx.x;
   const int c = K::COL ? (t % K::C) : (t / K::T);
@@ -422,7 +430,8 @@ __device__ __forceinline__ void fft_tile(const PassArgs& a, int w, float2* lds, 
     d[j] = src.load<AUX>(voff_in, sj_in * j);
   });
   if (io.conj_in) static_for<0, K::E>([&](auto J) { d[decltype(J)::value].y = -d[decltype(J)::value].y; });
-  static_for<0, K::P>([&](auto Pp) { run_pass<K, DIR, decltype(Pp)::value, SB>(d, lds, tt, c, tw); });
+  if constexpr (MODE < 2)
+    static_for<0, K::P>([&](auto Pp) { run_pass<K, DIR, decltype(Pp)::value, SB, MODE == 0>(d, lds, tt, c, tw); });
   if (active) {
     const float sc = io.scale;
     const float sy = io.conj_out ? -sc : sc;
@@ -433,14 +442,14 @@ __device__ __forceinline__ void fft_tile(const PassArgs& a, int w, float2* lds, 
   }
 }
 
-template <class K, int DIR, bool NT = false, int WPE = 1, int SB = 0>
+template <class K, int DIR, bool NT = false, int WPE = 1, int SB = 0, int MODE = 0>
 __global__ __launch_bounds__(K::THREADS) __attribute__((amdgpu_waves_per_eu(WPE))) void pass_kernel(PassArgs a) {
   static_assert(K::valid(), "invalid pass configuration");
   __shared__ float2 lds[K::LDS_ELEMS];
   const int w = K::COL ? xcd_remap(blockIdx.x, a.nblocks) : (int)blockIdx.x;
   TileIO io;
   io.scale = a.scale;
-  fft_tile<K, DIR, NT ? kAuxNontemporal : 0, SB>(a, w, lds, io);
+  fft_tile<K, DIR, NT ? kAuxNontemporal : 0, SB, MODE>(a, w, lds, io);
 }
 
 // Row pass with combine (first half of a split column transform, see
@@ -451,7 +460,10 @@ __global__ __launch_bounds__(K::THREADS) __attribute__((amdgpu_waves_per_eu(WPE)
 // are exchanged through LDS in Q rounds of L/Q positions; in each round every
 // thread owns L/(Q*THREADS) positions and all M1 rows of each. Only
 // io.conj_in is honoured (the output is an intermediate, never final).
-template <class K, int DIR, int AUX = 0, int SB = 0>
+// MODE as for fft_tile: 1 keeps the loads, both LDS exchanges and the stores
+// (no row FFTs, no combine DFT, no twiddles); 2 stores each loaded row to its
+// output row (row M2*c + m2 to row M1*m2 + c) without LDS.
+template <class K, int DIR, int AUX = 0, int SB = 0, int MODE = 0>
 __device__ __forceinline__ void rowc_tile(const PassArgs& a, int64_t w, float2* lds, TileIO io) {
   static_assert(K::valid() && !K::COL && K::C >= 2 && K::P > 1, "invalid combine configuration");
   constexpr int M1 = K::C;
@@ -479,14 +491,24 @@ __device__ __forceinline__ void rowc_tile(const PassArgs& a, int64_t w, float2* 
     d[j] = src.load<AUX>(voff_in, (uint32_t)(K::T * j) * 8u);
   });
   if (io.conj_in) static_for<0, K::E>([&](auto J) { d[decltype(J)::value].y = -d[decltype(J)::value].y; });
-  static_for<0, K::P>([&](auto Pp) { run_pass<K, DIR, decltype(Pp)::value, SB>(d, lds, tt, c, tw); });
+  if constexpr (MODE == 2) {
+    const uint32_t voff_out = (uint32_t)c * (uint32_t)(K::L * 8) + (uint32_t)tt * 8u;
+    static_for<0, K::E>([&](auto J) {
+      constexpr int j = decltype(J)::value;
+      dst.store(d[j], voff_out, (uint32_t)(K::T * j) * 8u);
+    });
+    return;
+  }
+  static_for<0, K::P>([&](auto Pp) { run_pass<K, DIR, decltype(Pp)::value, SB, MODE == 0>(d, lds, tt, c, tw); });
   float2 wk[M1];
-  static_for<1, M1>([&](auto Kk) {
-    constexpr int k1 = decltype(Kk)::value;
-    float2 w1 = a.twc[m2 * k1];
-    if constexpr (DIR > 0) w1.y = -w1.y;
-    wk[k1] = w1;
-  });
+  if constexpr (MODE == 0) {
+    static_for<1, M1>([&](auto Kk) {
+      constexpr int k1 = decltype(Kk)::value;
+      float2 w1 = a.twc[m2 * k1];
+      if constexpr (DIR > 0) w1.y = -w1.y;
+      wk[k1] = w1;
+    });
+  }
   static_for<0, K::Q>([&](auto H) {
     constexpr int h = decltype(H)::value;
     constexpr int EQ = K::E / K::Q;
@@ -504,21 +526,21 @@ __device__ __forceinline__ void rowc_tile(const PassArgs& a, int64_t w, float2* 
         constexpr int r = decltype(R)::value;
         x[r] = lds[rbase + r * K::ROWSTRIDE + K::lds_delta(K::THREADS * i)];
       });
-      dft<M1, DIR>(x);
+      if constexpr (MODE == 0) dft<M1, DIR>(x);
       const uint32_t voff = (uint32_t)(h * NQ + K::THREADS * i + t) * 8u;
       static_for<0, M1>([&](auto Kk) {
         constexpr int k1 = decltype(Kk)::value;
-        dst.store((k1 == 0) ? x[0] : cmul(x[k1], wk[k1]), voff, (uint32_t)(k1 * K::L) * 8u);
+        dst.store((k1 == 0 || MODE != 0) ? x[k1] : cmul(x[k1], wk[k1]), voff, (uint32_t)(k1 * K::L) * 8u);
       });
     });
     __syncthreads();
   });
 }
 
-template <class K, int DIR, int WPE = 1, int SB = 0, bool NT = false>
+template <class K, int DIR, int WPE = 1, int SB = 0, bool NT = false, int MODE = 0>
 __global__ __launch_bounds__(K::THREADS) __attribute__((amdgpu_waves_per_eu(WPE))) void rowc_kernel(PassArgs a) {
   __shared__ float2 lds[K::LDS_ELEMS];
-  rowc_tile<K, DIR, NT ? kAuxNontemporal : 0, SB>(a, blockIdx.x, lds, TileIO{});
+  rowc_tile<K, DIR, NT ? kAuxNontemporal : 0, SB, MODE>(a, blockIdx.x, lds, TileIO{});
 }
 
 // Whole-grid tile: one workgroup computes the complete 2D transform of one
@@ -636,6 +658,19 @@ hipError_t launch_rowc(const PassArgs& a, int dir, hipStream_t s, hipEvent_t t0,
   return hipGetLastError();
 }
 
+// Measurement variants (MODE 1: data movement without arithmetic, MODE 2:
+// loads and stores only) of a pass, launched like launch_pass/launch_rowc
+// with the forward sign (events optional).
+template <class K, int WPE, bool NT, bool COMBINE>
+hipError_t launch_probe(const PassArgs& a, int mode, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
+  void (*k)(PassArgs) = nullptr;
+  if constexpr (COMBINE) k = mode == 1 ? rowc_kernel<K, -1, WPE, 0, NT, 1> : rowc_kernel<K, -1, WPE, 0, NT, 2>;
+  else k = mode == 1 ? pass_kernel<K, -1, NT, WPE, 0, 1> : pass_kernel<K, -1, NT, WPE, 0, 2>;
+  if (t0 != nullptr || t1 != nullptr) return launch_timed(k, a, K::THREADS, s, t0, t1);
+  hipLaunchKernelGGL(k, dim3(a.nblocks), dim3(K::THREADS), 0, s, a);
+  return hipGetLastError();
+}
+
 // Shape metadata of a configuration (no kernel instantiated).
 template <class K>
 constexpr PassKernel meta() {
@@ -657,7 +692,8 @@ constexpr PassKernel meta() {
 // WPE: minimum waves per SIMD the compiler must allow (bounds VGPR use).
 // NT: nontemporal loads of the input (row passes read data not reused soon;
 // measured faster from HBM, slower when the data already sits in the MALL).
-template <class K, bool COMBINE = false, int WPE = 1, bool NT = !K::COL>
+// PROBE: also compile the measurement variants (launch_probe).
+template <class K, bool COMBINE = false, int WPE = 1, bool NT = !K::COL, bool PROBE = false>
 constexpr PassKernel describe() {
   PassKernel k{};
   k.combine = COMBINE ? K::C : 0;
@@ -675,6 +711,7 @@ constexpr PassKernel describe() {
   k.nt = NT ? 1 : 0;
   if constexpr (COMBINE) k.launch = &launch_rowc<K, WPE, NT>;
   else k.launch = &launch_pass<K, WPE, NT>;
+  if constexpr (PROBE) k.launch_probe = &launch_probe<K, WPE, NT, COMBINE>;
   return k;
 }
 

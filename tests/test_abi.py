@@ -87,6 +87,11 @@ def test_exec_rejects_null_and_dead_plans(L):
     assert "event" in L.last_error()
     assert L.lib.fft2d_exec_pass_timed(None, 8, 8, -1, 0, 16, 16, None) == 1
     assert L.lib.fft2d_exec_pass_timed(bogus, 8, 8, -1, 0, 16, 16, None) == 8
+    # the ablated pass checks its ablation and events first, then the plan like fft2d_exec_pass
+    assert L.lib.fft2d_exec_pass_ablated(bogus, 8, 8, 0, 3, None, None, None) == 3
+    assert L.lib.fft2d_exec_pass_ablated(bogus, 8, 8, 0, 1, 16, None, None) == 1
+    assert L.lib.fft2d_exec_pass_ablated(None, 8, 8, 0, 2, None, None, None) == 1
+    assert L.lib.fft2d_exec_pass_ablated(bogus, 8, 8, 0, 1, None, None, None) == 8
     assert L.lib.fft2d_destroy(bogus) == 8
     assert L.lib.fft2d_destroy(None) == 0
     buf = ctypes.create_string_buffer(16)
@@ -127,3 +132,18 @@ def test_product_package_does_not_import_the_oracle():
                 src = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in src and "from oracle" not in src, f
                 assert "fft_oracle" not in src, f
+
+
+def test_noalloc_rejects_bad_arguments_before_touching_the_gpu(L):
+    """fft2d_exec_noalloc validates sizes, direction and pointers on the host
+    (no device call is made for a rejected call)."""
+    f = L.lib.fft2d_exec_noalloc
+    assert f(1, 3, 8, 16, 32, -1, None) == 2
+    assert f(0, 8, 8, 16, 32, -1, None) == 2
+    assert f(1, 8, 32768, 16, 32, -1, None) == 2
+    assert f(1 << 30, 256, 256, 16, 32, -1, None) == 2  # beyond 2^35 points
+    assert f(1, 8, 8, None, 32, -1, None) == 1
+    assert f(1, 8, 8, 16, 32, 0, None) == 3
+    assert f(1, 8, 8, 12, 1024, -1, None) == 4
+    assert f(1, 64, 64, 16, 24, -1, None) == 9
+    assert "overlap" in L.last_error()

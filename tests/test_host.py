@@ -37,6 +37,13 @@ def test_pointer_array(F):
     assert F.pointer_array(a) is a  # an array of the right type passes through unconverted
 
 
+# demangled names of the round trip's four pass kernels, as rocprofv3 reports them
+_RC = "void fft2d::dev::rowc_kernel<fft2d::dev::Cfg<4096, 32, 4, 2, false, 16, 16, 16>, %d, 4, 0, true, 0>(fft2d::PassArgs)"
+_PK = ("void fft2d::dev::pass_kernel<fft2d::dev::Cfg<1024, 32, 16, 2, true, 16, 16, 4>, %d, false, 1, 0, 0>"
+       "(fft2d::PassArgs)")
+ROUND_TRIP_NAMES = [_RC % -1, _PK % -1, _RC % 1, _PK % 1]
+
+
 def _write_counters(path, rows):
     os.makedirs(path, exist_ok=True)
     with open(os.path.join(path, "run_counter_collection.csv"), "w", newline="") as fh:
@@ -52,8 +59,7 @@ def test_traffic_summary_scales_by_the_copy(tmp_path, monkeypatch):
     import bench
     grid = 4096 * 4096 * 8  # bytes of one grid
     kib = grid / 1024
-    names = ["fft2d::dev::rowc_kernel<a, -1>", "fft2d::dev::pass_kernel<b, -1>",
-             "fft2d::dev::rowc_kernel<a, 1>", "fft2d::dev::pass_kernel<b, 1>"]
+    names = ROUND_TRIP_NAMES
     fetch, write = [], []
     for step in range(2):
         for i, n in enumerate(names):
@@ -70,7 +76,7 @@ def test_traffic_summary_scales_by_the_copy(tmp_path, monkeypatch):
     assert "fetch_factor = 2.0000" in text and "write_factor = 1.0000" in text
     assert int(lines["fwd_row"][3]) == round(grid * 1.05) + grid
     assert int(lines["fwd_col"][3]) == 2 * grid
-    assert lines["inv_col"][-1].endswith("1>")
+    assert "pass_kernel" in " ".join(lines["inv_col"]) and ", 1, false" in " ".join(lines["inv_col"])
     # the bench reads the figure back only while the source hash matches
     prof = tmp_path / "profile.txt"
     prof.write_text("# header\n" + text + "\n")
@@ -99,20 +105,23 @@ def test_cpu_configs_reports_the_error_of_each_result(monkeypatch):
     gpu = {name: oracle.fft2_forward(synth.complex_grid(seed, shape)).astype(np.complex64)
            for name, shape, seed in bench.ORACLE_CASES}
     gpu["b"] = np.conj(gpu["b"])
+    monkeypatch.setattr(bench, "BACKWARD_CASE", ("d", (2, 8, 16), 3))
+    gpu["d"] = oracle.adjoint(synth.complex_grid(3, (2, 8, 16)), oracle.FORWARD).astype(np.complex64)
     gpu["batched"] = [oracle.fft2_forward(x).astype(np.complex64)
                       for x in synth.batched_grids(bench.BATCHED_SEED, synth.pow2_shapes(bench.BATCHED_SEED, 3))]
     out = bench.cpu_configs(gpu)
-    assert out["a"]["gpu_rel_l2"] < 1e-7 and out["c"]["gpu_rel_l2"] < 1e-7
-    assert out["b"]["gpu_rel_l2"] > 0.5
+    assert out["a"]["gpu_rel_l2"] < 1e-7 and out["c"]["gpu_rel_l2"] < 1e-7 and out["d"]["gpu_rel_l2"] < 1e-7
+    assert out["a"]["gpu_max_elem"] < 1e-6 and out["d"]["gpu_max_elem"] < 1e-6
+    assert out["b"]["gpu_rel_l2"] > 0.5 and out["b"]["gpu_max_elem"] > 0.5
     assert out["3 shapes 2^a x 2^b forward"]["gpu_rel_l2_max"] < 1e-7
+    assert out["3 shapes 2^a x 2^b forward"]["gpu_max_elem_max"] < 1e-6
 
 
 def test_counter_summary_means_per_pass(tmp_path):
     """--summarize-counters: dispatches assigned to passes in step order, the
     mean per launch of each counter, instruction counts per wave."""
     import bench
-    names = ["fft2d::dev::rowc_kernel<a, -1>", "fft2d::dev::pass_kernel<b, -1>",
-             "fft2d::dev::rowc_kernel<a, 1>", "fft2d::dev::pass_kernel<b, 1>"]
+    names = ROUND_TRIP_NAMES
     a, b = [], []
     for step in range(2):
         for i, n in enumerate(names):
@@ -169,3 +178,29 @@ def test_batched_schedule_invariants(tmp_path):
                    timeout=120)
     r = subprocess.run([exe, "120"], capture_output=True, text=True, timeout=300)
     assert r.returncode == 0 and r.stdout.startswith("ok "), r.stdout + r.stderr
+
+
+def test_counter_summaries_reject_a_shifted_trace(tmp_path):
+    """A profiled run with one dispatch missing (or one extra) would shift
+    every later counter onto the wrong pass: the summaries check each
+    dispatch's kernel (row or column pass, sign) and raise instead."""
+    import bench
+    rows = []
+    for step in range(2):
+        for i, n in enumerate(ROUND_TRIP_NAMES):
+            rows.append([10 + step * 4 + i, n, "SQ_WAVES", 100.0])
+    _write_counters(tmp_path / "ok", rows)
+    assert "pass inv_col" in bench.summarize_counters(str(tmp_path / "ok"))
+    _write_counters(tmp_path / "shifted", rows[1:])
+    with pytest.raises(ValueError):
+        bench.summarize_counters(str(tmp_path / "shifted"))
+    # measurement variants and other kernels are not passes of the sequence
+    probe = ROUND_TRIP_NAMES[0].replace("true, 0>", "true, 2>")
+    assert bench.kernel_role(probe) == ("row-probe", -1)
+    _write_counters(tmp_path / "extra", rows + [[99, probe, "SQ_WAVES", 1.0], [98, "copyBuffer", "SQ_WAVES", 1.0]])
+    assert bench.summarize_counters(str(tmp_path / "extra")) == bench.summarize_counters(str(tmp_path / "ok"))
+    fwd = [[i, n, "SQ_WAVES", 1.0] for i, n in enumerate(ROUND_TRIP_NAMES[:2] * 3)]
+    _write_counters(tmp_path / "fwd", fwd)
+    assert "pass fwd_col" in bench.summarize_counters(str(tmp_path / "fwd"), roles=bench.FORWARD_ROLES)
+    with pytest.raises(ValueError):
+        bench.summarize_counters(str(tmp_path / "fwd"))  # a forward-only trace is not a round trip
