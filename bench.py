@@ -606,15 +606,40 @@ def time_backward(F, torch, batch, rows, cols, steps, warmup, seed):
             "backward_over_plain": bwd / fwd, "plain_gflops": fl / fwd / 1e6, "backward_gflops": fl / bwd / 1e6}
 
 
+def _batched_plan(F, shapes, tune, cache):
+    """A batched plan made with FFT2D_TUNE=`tune` and the tuning cache at `cache`."""
+    saved = {k: os.environ.get(k) for k in ("FFT2D_TUNE", "FFT2D_TUNE_CACHE")}
+    os.environ["FFT2D_TUNE"] = tune
+    os.environ["FFT2D_TUNE_CACHE"] = cache
+    try:
+        return F.BatchedPlan(shapes)
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+
+
 def time_batched(F, torch, steps, warmup, seed):
-    """512 transforms of 2^a x 2^b (a, b in [6, 11] from `seed`): one graph replay of the
-    persistent kernel against 512 fft2d_exec calls (two kernel launches each) on one stream."""
+    """512 transforms of 2^a x 2^b (a, b in [6, 11] from `seed`): one graph
+    replay of the persistent kernel, with the autotuner's choice (grid size,
+    item order, group size and the radix/tile variant of every length, tuned
+    afresh into a scratch cache file) and with the untuned defaults, against
+    512 fft2d_exec calls (two kernel launches each) on one stream."""
+    import tempfile
+
     import synth
     shapes = synth.pow2_shapes(seed, 512)
     xs = [torch.from_numpy(x).to("cuda") for x in synth.batched_grids(seed, shapes)]
     ys = [torch.empty_like(x) for x in xs]
     zs = [torch.empty_like(x) for x in xs]
-    plan = F.BatchedPlan(shapes)
+    with tempfile.TemporaryDirectory() as tmp:
+        cache = os.path.join(tmp, "tune.txt")
+        t0 = time.perf_counter()
+        plan = _batched_plan(F, shapes, "full", cache)
+        tune_s = time.perf_counter() - t0
+        default = _batched_plan(F, shapes, "off", cache)
     stream = torch.cuda.current_stream()
     sh = int(stream.cuda_stream)
     iptr = [x.data_ptr() for x in xs]
@@ -622,13 +647,6 @@ def time_batched(F, torch, steps, warmup, seed):
     oarr = F.pointer_array([y.data_ptr() for y in ys])
     plans = [F.get_plan(1, r, c, xs[0].device) for r, c in shapes]
     zptr = [z.data_ptr() for z in zs]
-
-    def batched():
-        plan.exec_ptrs(iarr, oarr, F.FORWARD, sh)
-
-    def plain():
-        for p, a, b in zip(plans, iptr, zptr):
-            F.fft2d_exec(p.handle, a, b, F.FORWARD, sh)
 
     def run(fn):
         for _ in range(warmup):
@@ -643,18 +661,25 @@ def time_batched(F, torch, steps, warmup, seed):
         torch.cuda.synchronize()
         return a.elapsed_time(b) / steps
 
-    t_b = run(batched)
+    def plain():
+        for p, a, b in zip(plans, iptr, zptr):
+            F.fft2d_exec(p.handle, a, b, F.FORWARD, sh)
+
+    t_d = run(lambda: default.exec_ptrs(iarr, oarr, F.FORWARD, sh))
+    t_b = run(lambda: plan.exec_ptrs(iarr, oarr, F.FORWARD, sh))
     t_p = run(plain)
     num = sum(float(torch.linalg.vector_norm(y - z)) ** 2 for y, z in zip(ys, zs)) ** 0.5
     den = sum(float(torch.linalg.vector_norm(z)) ** 2 for z in zs) ** 0.5
     points = sum(r * c for r, c in shapes)
     fl = sum(flops_2d(r, c) for r, c in shapes)
     res = {"workload": "512 forward 2D FFTs of 2^a x 2^b, a, b in [6, 11] from seed %d, %d points" % (seed, points),
-           "batched_ms": t_b, "plain_512_launches_ms": t_p, "speedup": t_p / t_b,
+           "batched_ms": t_b, "batched_untuned_ms": t_d, "tuned_over_untuned": t_b / t_d, "tuning_s": tune_s,
+           "plain_512_launches_ms": t_p, "speedup": t_p / t_b,
            "batched_gflops": fl / t_b / 1e6, "plain_gflops": fl / t_p / 1e6,
            "batched_hbm_gbps": 32.0 * points / t_b / 1e6,
-           "batched_vs_plain_rel_l2": num / den, "plan": plan.describe()}
+           "batched_vs_plain_rel_l2": num / den, "plan": plan.describe(), "plan_untuned": default.describe()}
     plan.close()
+    default.close()
     return res
 
 

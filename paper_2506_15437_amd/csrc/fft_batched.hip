@@ -38,6 +38,7 @@
 #include "fft_batched.h"
 #include "fft_pass.hpp"
 #include "fft_schedule.hpp"
+#include "fft_tune_cache.hpp"
 
 #include <algorithm>
 #include <cmath>
@@ -58,7 +59,12 @@ namespace {
 using namespace dev;
 
 constexpr int kThreads = 512;
-constexpr int kNumCfg = 48;  // id = mode * 16 + log2(L); mode 0 = row, 1 = column, 2 = row with combine
+// id = variant * 48 + mode * 16 + log2(L); mode 0 = row, 1 = column, 2 = row
+// with combine; variant 0 or 1 (a second radix schedule / tile shape for rows
+// and columns of 32 ... 16384 points, chosen per length by the autotuner).
+constexpr int kNumCfg = 96;
+constexpr int kVariantStride = 48;
+constexpr int kMinVariantLog2 = 5;  // lengths below 32 have one configuration
 
 // Row configurations (512 threads each).
 using BR2 = Cfg<2, 2, 512, 1, false, 2>;
@@ -98,6 +104,30 @@ using BRC2048 = Cfg<2048, 32, 8, 2, false, 16, 16, 8>;
 using BRC4096 = Cfg<4096, 32, 4, 2, false, 16, 16, 16>;
 using BRC8192 = Cfg<8192, 32, 2, 2, false, 16, 16, 32>;
 
+// Variant-1 configurations (512 threads each): the other points-per-thread
+// count, hence the other tile size (4096 / 8192 / 16384 points) and, for
+// columns, the other row-segment width, or another radix order.
+using BR32v = Cfg<32, 16, 256, 1, false, 16, 2>;
+using BR64v = Cfg<64, 16, 128, 1, false, 16, 4>;
+using BR128v = Cfg<128, 8, 32, 1, false, 8, 8, 2>;
+using BR256v = Cfg<256, 32, 64, 2, false, 8, 32>;
+using BR512v = Cfg<512, 32, 32, 2, false, 16, 32>;
+using BR1024v = Cfg<1024, 32, 16, 2, false, 16, 16, 4>;
+using BR2048v = Cfg<2048, 32, 8, 2, false, 16, 16, 8>;
+using BR4096v = Cfg<4096, 32, 4, 2, false, 16, 16, 16>;
+using BR8192v = Cfg<8192, 32, 2, 2, false, 16, 16, 32>;
+using BR16384v = Cfg<16384, 32, 1, 2, false, 16, 16, 4, 16>;
+using BC32v = Cfg<32, 16, 256, 1, true, 16, 2>;
+using BC64v = Cfg<64, 16, 128, 1, true, 16, 4>;
+using BC128v = Cfg<128, 8, 32, 1, true, 8, 8, 2>;
+using BC256v = Cfg<256, 32, 64, 2, true, 8, 32>;
+using BC512v = Cfg<512, 32, 32, 2, true, 16, 32>;
+using BC1024v = Cfg<1024, 16, 8, 1, true, 16, 16, 4>;
+using BC2048v = Cfg<2048, 16, 4, 1, true, 16, 16, 8>;
+using BC4096v = Cfg<4096, 16, 2, 1, true, 16, 16, 16>;
+using BC8192v = Cfg<8192, 16, 1, 1, true, 16, 16, 16, 2>;
+using BC16384v = Cfg<16384, 32, 1, 2, true, 16, 16, 4, 16>;
+
 template <class... Ks>
 constexpr int max_lds() {
   int m = 1;
@@ -107,7 +137,9 @@ constexpr int max_lds() {
 constexpr int kLdsElems = max_lds<BR2, BR4, BR8, BR16, BR32, BR64, BR128, BR256, BR512, BR1024, BR2048, BR4096,
                                   BR8192, BR16384, BC2, BC4, BC8, BC16, BC32, BC64, BC128, BC256, BC512, BC1024,
                                   BC2048, BC4096, BC8192, BC16384, BRC512, BRC1024, BRC2048, BRC4096,
-                                  BRC8192>();
+                                  BRC8192, BR32v, BR64v, BR128v, BR256v, BR512v, BR1024v, BR2048v, BR4096v,
+                                  BR8192v, BR16384v, BC32v, BC64v, BC128v, BC256v, BC512v, BC1024v, BC2048v,
+                                  BC4096v, BC8192v, BC16384v>();
 static_assert(kLdsElems * 8 <= 80 * 1024, "two batched workgroups must fit one CU's LDS");
 
 struct BatchDesc {
@@ -325,6 +357,26 @@ __device__ __forceinline__ void run_tile(int cfg, const float2* in, float2* out,
     case 28: tile<BC4096>(FFT2D_TILE_ARGS); break;
     case 29: tile<BC8192>(FFT2D_TILE_ARGS); break;
     case 30: tile<BC16384>(FFT2D_TILE_ARGS); break;
+    case 53: tile<BR32v>(FFT2D_TILE_ARGS); break;
+    case 54: tile<BR64v>(FFT2D_TILE_ARGS); break;
+    case 55: tile<BR128v>(FFT2D_TILE_ARGS); break;
+    case 56: tile<BR256v>(FFT2D_TILE_ARGS); break;
+    case 57: tile<BR512v>(FFT2D_TILE_ARGS); break;
+    case 58: tile<BR1024v>(FFT2D_TILE_ARGS); break;
+    case 59: tile<BR2048v>(FFT2D_TILE_ARGS); break;
+    case 60: tile<BR4096v>(FFT2D_TILE_ARGS); break;
+    case 61: tile<BR8192v>(FFT2D_TILE_ARGS); break;
+    case 62: tile<BR16384v>(FFT2D_TILE_ARGS); break;
+    case 69: tile<BC32v>(FFT2D_TILE_ARGS); break;
+    case 70: tile<BC64v>(FFT2D_TILE_ARGS); break;
+    case 71: tile<BC128v>(FFT2D_TILE_ARGS); break;
+    case 72: tile<BC256v>(FFT2D_TILE_ARGS); break;
+    case 73: tile<BC512v>(FFT2D_TILE_ARGS); break;
+    case 74: tile<BC1024v>(FFT2D_TILE_ARGS); break;
+    case 75: tile<BC2048v>(FFT2D_TILE_ARGS); break;
+    case 76: tile<BC4096v>(FFT2D_TILE_ARGS); break;
+    case 77: tile<BC8192v>(FFT2D_TILE_ARGS); break;
+    case 78: tile<BC16384v>(FFT2D_TILE_ARGS); break;
     default: break;
   }
 }
@@ -462,8 +514,24 @@ const PassKernel* cfg_table() {
       bdesc<BC16384>(), PassKernel{},  PassKernel{},   PassKernel{},    PassKernel{},    PassKernel{},
       PassKernel{},   PassKernel{},    PassKernel{},    PassKernel{},   PassKernel{},    bdesc<BRC512>(),
       bdesc<BRC1024>(), bdesc<BRC2048>(), bdesc<BRC4096>(), bdesc<BRC8192>(), PassKernel{}, PassKernel{},
+      // variant 1: ids 48 + mode * 16 + log2(L)
+      PassKernel{}, PassKernel{}, PassKernel{}, PassKernel{}, PassKernel{}, bdesc<BR32v>(),
+      bdesc<BR64v>(), bdesc<BR128v>(), bdesc<BR256v>(), bdesc<BR512v>(), bdesc<BR1024v>(), bdesc<BR2048v>(),
+      bdesc<BR4096v>(), bdesc<BR8192v>(), bdesc<BR16384v>(), PassKernel{}, PassKernel{}, PassKernel{},
+      PassKernel{}, PassKernel{}, PassKernel{}, bdesc<BC32v>(), bdesc<BC64v>(), bdesc<BC128v>(),
+      bdesc<BC256v>(), bdesc<BC512v>(), bdesc<BC1024v>(), bdesc<BC2048v>(), bdesc<BC4096v>(), bdesc<BC8192v>(),
+      bdesc<BC16384v>(), PassKernel{}, PassKernel{}, PassKernel{}, PassKernel{}, PassKernel{},
+      PassKernel{}, PassKernel{}, PassKernel{}, PassKernel{}, PassKernel{}, PassKernel{},
+      PassKernel{}, PassKernel{}, PassKernel{}, PassKernel{}, PassKernel{}, PassKernel{},
   };
   return tab;
+}
+
+// Configuration id of an FFT of length L along rows (mode 0) or columns
+// (mode 1) in the given variant; lengths below 32 have variant 0 only.
+int cfg_id(int variant, int mode, int log2_len) {
+  const int v = log2_len >= kMinVariantLog2 ? variant : 0;
+  return v * kVariantStride + mode * 16 + log2_len;
 }
 
 int ilog2i(int64_t n) {
@@ -516,6 +584,7 @@ struct BatchedPlan {
   int grid_mult = 2;
   int order = 1;
   int group_kib = 256;  // target data per item group
+  unsigned char variant[2][tune::kVariantSlots] = {};  // radix/tile variant per row / column length (log2)
   std::string tune_source = "default";
   // device state
   BatchDesc* d_desc = nullptr;
@@ -647,32 +716,7 @@ std::string cache_path() {
   return std::string(home) + "/.cache/fft2d_tune.txt";
 }
 
-bool valid_group_kib(int g) { return g == 64 || g == 256 || g == 1024; }
-
-// Cache lines: "<key hex> <grid_mult> <order> <group_kib>"; malformed lines are ignored.
-bool cache_lookup(const std::string& key, int* mult, int* order, int* group_kib) {
-  const std::string path = cache_path();
-  if (path.empty()) return false;
-  std::ifstream in(path);
-  std::string line;
-  bool found = false;
-  while (std::getline(in, line)) {
-    std::istringstream ls(line);
-    std::string k;
-    int m = 0, o = -1, g = 0;
-    if (!(ls >> k >> m >> o >> g)) continue;
-    // grid multipliers 1 ... 3 are the ones the plan's XCC probe checked
-    if (k == key && m >= 1 && m <= 3 && (o == 0 || o == 1) && valid_group_kib(g)) {
-      *mult = m;
-      *order = o;
-      *group_kib = g;
-      found = true;
-    }
-  }
-  return found;
-}
-
-void cache_store(const std::string& key, int mult, int order, int group_kib) {
+void cache_store(const std::string& key, const tune::Choice& c) {
   const std::string path = cache_path();
   if (path.empty()) return;
   std::ofstream out(path, std::ios::app);
@@ -682,7 +726,50 @@ void cache_store(const std::string& key, int mult, int order, int group_kib) {
     (void)::mkdir(path.substr(0, slash).c_str(), 0755);  // one level, best effort
     out.open(path, std::ios::app);
   }
-  if (out) out << key << " " << mult << " " << order << " " << group_kib << "\n";
+  if (out) out << tune::format_line(key, c) << "\n";
+}
+
+// Configuration ids and tile counts of every transform for the plan's
+// current variant choice (whole-grid items keep the variant-0 tables their
+// kernels use), written to the host descriptors as well.
+void assign_configs(BatchedPlan* bp) {
+  const PassKernel* tab = cfg_table();
+  for (int64_t i = 0; i < bp->count; ++i) {
+    const size_t k = (size_t)i;
+    const int M = bp->rows[k], N = bp->cols[k], m1 = bp->m1[k];
+    const bool whole = bp->grid[k] != 0;
+    const int ln = ilog2i(N), lm = ilog2i(M / m1);
+    const int rc = m1 > 1 ? 32 + ln : (N > 1 ? cfg_id(whole ? 0 : bp->variant[0][ln], 0, ln) : 0);
+    const int cc = M > 1 ? cfg_id(whole ? 0 : bp->variant[1][lm], 1, lm) : 0;
+    bp->row_cfg[k] = rc;
+    bp->col_cfg[k] = cc;
+    // a whole-grid item has no row or column tiles (and nothing to wait for)
+    bp->nrow[k] = !whole && N > 1 ? (M + tab[rc].C - 1) / tab[rc].C : 0;
+    bp->ncol[k] = !whole && M > 1 ? (int)(((int64_t)m1 * N + tab[cc].C - 1) / tab[cc].C) : 0;
+    if (bp->h_desc) {
+      bp->h_desc[i].row_cfg = rc;
+      bp->h_desc[i].col_cfg = cc;
+      bp->h_desc[i].nrow_items = bp->nrow[k];
+    }
+  }
+}
+
+// Lengths (mode, log2 L) whose variant the tuner may choose: those that some
+// transform runs as row or column tiles with more than one configuration.
+std::vector<std::pair<int, int>> tunable_lengths(const BatchedPlan& bp) {
+  bool used[2][tune::kVariantSlots] = {};
+  for (int64_t i = 0; i < bp.count; ++i) {
+    const size_t k = (size_t)i;
+    if (bp.grid[k]) continue;
+    const int N = bp.cols[k], M = bp.rows[k], m1 = bp.m1[k];
+    if (m1 == 1 && N > 1) used[0][ilog2i(N)] = true;
+    if (M > 1) used[1][ilog2i(M / m1)] = true;
+  }
+  std::vector<std::pair<int, int>> v;
+  for (int m = 0; m < 2; ++m)
+    for (int j = kMinVariantLog2; j < tune::kVariantSlots; ++j)
+      if (used[m][j]) v.push_back({m, j});
+  return v;
 }
 
 // Time one candidate (grid multiplier, order, group size) on scratch buffers; median of reps.
@@ -871,21 +958,37 @@ fft2d_status create_batched(int64_t count, const int64_t* rows, const int64_t* c
     d.pad = 0;
   }
 
-  // Autotuner: persistent grid size (workgroups per CU) and item order,
+  // Autotuner: persistent grid size (workgroups per CU), item order and group
+  // size, then the radix/tile variant of every row and column length,
   // measured on scratch buffers of this plan's shapes, cached per shape set.
+  // FFT2D_BATCH_VARIANT=0|1 fixes every length's variant (no variant search).
   const char* tune_env = std::getenv("FFT2D_TUNE");
   const std::string mode = tune_env ? tune_env : "cached";
+  const char* var_env = std::getenv("FFT2D_BATCH_VARIANT");
+  const int forced_variant = (var_env && (std::string(var_env) == "0" || std::string(var_env) == "1"))
+                                 ? (var_env[0] - '0') : -1;
+  if (forced_variant >= 0)
+    for (int m = 0; m < 2; ++m)
+      for (int j = 0; j < tune::kVariantSlots; ++j) bp->variant[m][j] = (unsigned char)forced_variant;
+  assign_configs(bp);
   std::ostringstream keys;
-  keys << "gfx950|v4|" << (bp->n_split ? "split|" : "") << (bp->n_grid ? "whole|" : "") << shape_signature(*bp);
+  keys << "gfx950|v5|" << (bp->n_split ? "split|" : "") << (bp->n_grid ? "whole|" : "")
+       << (forced_variant >= 0 ? "variant" + std::to_string(forced_variant) + "|" : "") << shape_signature(*bp);
   char keyhex[32];
   std::snprintf(keyhex, sizeof(keyhex), "%016llx", (unsigned long long)fnv1a(keys.str()));
   bool have = false;
+  tune::Choice cached;
   if (mode == "off") {
     have = true;
     bp->tune_source = "default";
-  } else if (mode != "full" && cache_lookup(keyhex, &bp->grid_mult, &bp->order, &bp->group_kib)) {
+  } else if (mode != "full" && tune::lookup(cache_path(), keyhex, &cached)) {
     have = true;
     bp->tune_source = "cache";
+    bp->grid_mult = cached.grid_mult;
+    bp->order = cached.order;
+    bp->group_kib = cached.group_kib;
+    if (forced_variant < 0) std::memcpy(bp->variant, cached.variant, sizeof(bp->variant));
+    assign_configs(bp);
   }
   if (!have) {
     float2 *sin = nullptr, *sout = nullptr;
@@ -901,8 +1004,11 @@ fft2d_status create_batched(int64_t count, const int64_t* rows, const int64_t* c
       set_desc_ptrs(bp, i, sin + off, sout + off);
       off += (int64_t)bp->rows[(size_t)i] * bp->cols[(size_t)i];
     }
-    e = hipMemcpyAsync(bp->d_desc, bp->h_desc, (size_t)count * sizeof(BatchDesc), hipMemcpyHostToDevice,
-                       bp->cap_stream);
+    auto upload_desc = [&]() {
+      return hipMemcpyAsync(bp->d_desc, bp->h_desc, (size_t)count * sizeof(BatchDesc), hipMemcpyHostToDevice,
+                            bp->cap_stream);
+    };
+    e = upload_desc();
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (e == hipSuccess) e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
@@ -921,6 +1027,24 @@ fft2d_status create_batched(int64_t count, const int64_t* rows, const int64_t* c
               bp->group_kib = g;
             }
           }
+      // variant descent: flip one length at a time, keep a flip that is at least 1 % faster
+      if (forced_variant < 0) {
+        for (const auto& ml : tunable_lengths(*bp)) {
+          unsigned char& v = bp->variant[ml.first][ml.second];
+          v ^= 1u;
+          assign_configs(bp);
+          float t = 1e30f;
+          if ((e = upload_desc()) == hipSuccess)
+            t = time_candidate(bp, bp->grid_mult, bp->order, bp->group_kib, bp->cap_stream, e0, e1);
+          if (e != hipSuccess) break;
+          if (t < 0.99f * best) {
+            best = t;
+          } else {
+            v ^= 1u;
+          }
+        }
+        assign_configs(bp);
+      }
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
@@ -931,7 +1055,12 @@ fft2d_status create_batched(int64_t count, const int64_t* rows, const int64_t* c
     if (e != hipSuccess) return hipfail(e, "autotune");
     if (best >= 1e29f) return fail(FFT2D_ERR_HIP, "autotune: every candidate failed");
     bp->tune_source = "tuned";
-    cache_store(keyhex, bp->grid_mult, bp->order, bp->group_kib);
+    tune::Choice c;
+    c.grid_mult = bp->grid_mult;
+    c.order = bp->order;
+    c.group_kib = bp->group_kib;
+    std::memcpy(c.variant, bp->variant, sizeof(c.variant));
+    cache_store(keyhex, c);
   }
   if ((e = upload_schedule(bp, build_schedule(*bp, bp->order, bp->group_kib))) != hipSuccess)
     return hipfail(e, "item table");
@@ -1036,6 +1165,16 @@ std::string describe_batched(const BatchedPlan* bp) {
      << " queues=" << bp->nq
      << (bp->fenced ? " fenced" : " xcd-local") << " grid=" << bp->grid_mult << "x" << bp->num_cu
      << " order=" << (bp->order ? "chunked" : "rows-then-columns") << " tune=" << bp->tune_source
+     << " variants=";
+  // the radix/tile variant chosen for every row (r) and column (c) length that has two
+  bool first = true;
+  for (const auto& ml : tunable_lengths(*bp)) {
+    os << (first ? "" : ",") << (ml.first ? "c" : "r") << (1 << ml.second) << ":"
+       << (int)bp->variant[ml.first][ml.second];
+    first = false;
+  }
+  if (first) os << "none";
+  os
      << " threads=" << kThreads << " lds=" << kLdsElems * 8;
   return os.str();
 }

@@ -316,3 +316,82 @@ def test_batched_undrained_queue_is_reported(F, monkeypatch):
         w.report()
     finally:
         plan.close()
+
+
+# every row and column length 32 ... 16384 that has two radix/tile variants, with partly filled tiles,
+# plus split transforms (their column lengths take variants too)
+VARIANT_SHAPES = [(4, 32), (32, 4), (8, 64), (64, 8), (16, 128), (128, 16), (8, 256), (256, 8), (4, 512),
+                  (512, 4), (2, 1024), (1024, 2), (2, 2048), (2048, 2), (2, 4096), (4096, 2), (2, 8192),
+                  (8192, 2), (1, 16384), (16384, 1), (2048, 1024), (1024, 512), (64, 64)]
+
+
+@pytest.mark.parametrize("variant", ["0", "1"])
+def test_batched_every_variant(F, variant, monkeypatch):
+    """Each radix/tile variant of the batched kernel's configuration table,
+    forced for every length (FFT2D_BATCH_VARIANT), forward and inverse against
+    the oracle."""
+    monkeypatch.setenv("FFT2D_TUNE", "off")
+    monkeypatch.setenv("FFT2D_BATCH_VARIANT", variant)
+    say("case batched variant %s" % variant)
+    xs = synth.batched_grids(17, VARIANT_SHAPES)
+    plan = F.BatchedPlan(VARIANT_SHAPES)
+    try:
+        desc = plan.describe()
+        say(desc)
+        listed = desc.split(" variants=")[1].split()[0].split(",")
+        assert len(listed) >= 20 and all(v.endswith(":" + variant) for v in listed), desc
+        _, ys = _run(F, plan, xs, F.FORWARD)
+        _, zs = _run(F, plan, xs, F.INVERSE)
+        wf, wi = Worst("batched variant %s fwd" % variant), Worst("batched variant %s inv" % variant)
+        for x, y, z, s in zip(xs, ys, zs, VARIANT_SHAPES):
+            wf.add(host(y), oracle.fft2_forward(x), s)
+            wi.add(host(z), oracle.ifft2(x), s)
+        wf.report()
+        wi.report()
+    finally:
+        plan.close()
+
+
+def test_batched_tuner_choice_is_cached(F, monkeypatch, tmp_path):
+    """FFT2D_TUNE=full tunes grid, order, group size and every length's
+    variant, and appends the choice to the cache; a second plan of the same
+    shapes takes it from the cache (same description) and computes the same
+    result bit for bit; a cache file of junk makes the plan tune again."""
+    import torch
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("FFT2D_TUNE_CACHE", str(cache))
+    shapes = synth.pow2_shapes(18, 48)
+    say("case batched tuner cache, %d points" % sum(r * c for r, c in shapes))
+    xs = [dev(x) for x in synth.batched_grids(18, shapes)]
+    monkeypatch.setenv("FFT2D_TUNE", "full")
+    a = F.BatchedPlan(shapes)
+    try:
+        da = a.describe()
+        say(da)
+        assert "tune=tuned" in da and " variants=" in da
+        ya = a(xs, F.FORWARD)
+        torch.cuda.synchronize()
+    finally:
+        a.close()
+    assert len(cache.read_text().splitlines()) == 1
+    monkeypatch.setenv("FFT2D_TUNE", "cached")
+    b = F.BatchedPlan(shapes)
+    try:
+        db = b.describe()
+        assert "tune=cache" in db and db.replace("tune=cache", "tune=tuned") == da, (da, db)
+        yb = b(xs, F.FORWARD)
+        torch.cuda.synchronize()
+        for u, v in zip(ya, yb):
+            assert torch.equal(u, v)
+    finally:
+        b.close()
+    cache.write_bytes(bytes(range(256)) * 8)
+    c = F.BatchedPlan(shapes)
+    try:
+        assert "tune=tuned" in c.describe()
+    finally:
+        c.close()
+    w = Worst("batched tuned plan")
+    for x, y, s in zip(xs, ya, shapes):
+        w.add(host(y), oracle.fft2_forward(host(x)), s)
+    w.report()

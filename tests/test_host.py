@@ -204,3 +204,17 @@ def test_counter_summaries_reject_a_shifted_trace(tmp_path):
     assert "pass fwd_col" in bench.summarize_counters(str(tmp_path / "fwd"), roles=bench.FORWARD_ROLES)
     with pytest.raises(ValueError):
         bench.summarize_counters(str(tmp_path / "fwd"))  # a forward-only trace is not a round trip
+
+
+def test_tune_cache_parsing(tmp_path):
+    """The batched tuner's cache (csrc/fft_tune_cache.hpp): a missing, empty,
+    binary or malformed cache file yields no choice, so the plan tunes again
+    (or keeps its defaults with FFT2D_TUNE=off) rather than using bad values;
+    a valid line is found among junk and the last one for a key wins
+    (tests/c/tune_cache_check.cpp)."""
+    exe = str(tmp_path / "tune_cache_check")
+    src = os.path.join(ROOT, "tests", "c", "tune_cache_check.cpp")
+    subprocess.run(["g++", "-std=c++17", "-O2", "-Wall", "-Wextra", "-Werror", src, "-o", exe], check=True,
+                   timeout=120)
+    r = subprocess.run([exe, str(tmp_path)], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 0 and r.stdout.strip() == "ok", r.stdout + r.stderr
