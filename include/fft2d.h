@@ -243,6 +243,33 @@ fft2d_status fft2d_exec_pass_timed(fft2d_plan_t plan, const void* in, void* out,
 fft2d_status fft2d_exec_pass_ablated(fft2d_plan_t plan, const void* in, void* out, int pass, int ablation,
                                      void* start_event, void* stop_event, void* stream);
 
+/* Methods of fft2d_probe_dft16. */
+#define FFT2D_DFT16_BUTTERFLY 0 /* radix-2 butterflies on the vector ALU (the library's radix-16 stage) */
+#define FFT2D_DFT16_MFMA 1      /* dense DFT matrix on the matrix cores (v_mfma_f32_16x16x4_f32) */
+
+/*
+ * fft2d_probe_dft16 -- a measurement aid for the choice between the vector
+ * ALU and the matrix cores for a radix-16 stage (the paper runs its FFT
+ * arithmetic on either the vector unit or the matrix engine of a Tensix core,
+ * Section 4). Applies x <- Pi F x `reps` times to each of `count` 16-point
+ * complex64 vectors held in registers, where F is the unscaled forward
+ * 16-point DFT and Pi moves point 4q + r to point q + 4r, scaling by 2^-16
+ * (exactly) after every 8 applications: out = (Pi F / 4)^reps in. The work is
+ * arithmetic only (one load and one store of each vector), so
+ * count * reps / elapsed time is the method's DFT16 rate.
+ *   method : FFT2D_DFT16_BUTTERFLY or FFT2D_DFT16_MFMA (else
+ *            FFT2D_ERR_INVALID_DIRECTION);
+ *   in, out : device pointers to count * 16 complex64, 8-byte aligned,
+ *            vector v at points 16 v ... 16 v + 15; may alias exactly;
+ *   count  : multiple of 64 in [64, 2^26]; reps : multiple of 8 in [8, 4096]
+ *            (else FFT2D_ERR_INVALID_SIZE);
+ *   start_event, stop_event : both null, or hipEvent_t handles bound to the
+ *            kernel launch as in fft2d_exec_pass_timed.
+ * Only enqueues work on `stream`; no plan is needed.
+ */
+fft2d_status fft2d_probe_dft16(int method, const void* in, void* out, int64_t count, int reps, void* start_event,
+                               void* stop_event, void* stream);
+
 /* fft2d_destroy -- free a plan and its device memory. NULL is a no-op. Waits for
  * no stream: the caller must make sure no enqueued work still uses the plan. */
 fft2d_status fft2d_destroy(fft2d_plan_t plan);

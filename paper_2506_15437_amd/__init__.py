@@ -19,7 +19,8 @@ Torch-level API:
 C-ABI-level API (same names as the C functions, pointers as ints):
     fft2d_plan, fft2d_plan_batched, fft2d_exec, fft2d_exec_pass, fft2d_exec_pass_timed,
     fft2d_exec_batched, fft2d_backward, fft2d_destroy, fft2d_plan_describe,
-    fft2d_exec_noalloc (no plan, no allocation), fft2d_exec_pass_ablated (measurement aid)
+    fft2d_exec_noalloc (no plan, no allocation), fft2d_exec_pass_ablated and
+    fft2d_probe_dft16 (measurement aids)
 """
 
 from __future__ import annotations
@@ -27,7 +28,8 @@ from __future__ import annotations
 _LIB_NAMES = ("EXPORTS", "FORWARD", "INVERSE", "LIB_PATH", "MAX_LEN", "Fft2dError", "fft2d_plan",
               "fft2d_plan_batched", "fft2d_exec", "fft2d_exec_pass", "fft2d_exec_pass_timed", "fft2d_exec_batched",
               "fft2d_backward", "fft2d_destroy", "fft2d_plan_describe", "fft2d_plan_twiddles", "fft2d_exec_noalloc", "NOALLOC_WORK_BYTES", "fft2d_exec_pass_ablated",
-              "ABLATE_ARITHMETIC", "ABLATE_EXCHANGE", "status_string",
+              "ABLATE_ARITHMETIC", "ABLATE_EXCHANGE", "fft2d_probe_dft16", "DFT16_BUTTERFLY", "DFT16_MFMA",
+              "status_string",
               "last_error", "version", "pointer_array")
 _API_NAMES = ("Plan", "BatchedPlan", "get_plan", "fft2", "ifft2", "fft2_batched", "FFT2Function", "fft2_diff")
 

@@ -44,7 +44,7 @@ EXPORTS = ("fft2d_plan", "fft2d_plan_batched", "fft2d_exec", "fft2d_exec_pass", 
            "fft2d_exec_pass_ablated",
            "fft2d_exec_batched",
            "fft2d_backward", "fft2d_destroy", "fft2d_status_string", "fft2d_last_error", "fft2d_plan_describe",
-           "fft2d_plan_twiddles", "fft2d_exec_noalloc", "fft2d_version")
+           "fft2d_plan_twiddles", "fft2d_exec_noalloc", "fft2d_probe_dft16", "fft2d_version")
 
 
 class Fft2dError(RuntimeError):
@@ -79,12 +79,14 @@ def _load():
     lib.fft2d_plan_describe.argtypes = [vp, ctypes.c_char_p, i64]
     lib.fft2d_plan_twiddles.argtypes = [vp, ci, vp, i64, ctypes.POINTER(i64)]
     lib.fft2d_exec_noalloc.argtypes = [i64, i64, i64, vp, vp, ci, vp]
+    lib.fft2d_probe_dft16.argtypes = [ci, vp, vp, i64, ci, vp, vp, vp]
     lib.fft2d_version.argtypes = []
     lib.fft2d_version.restype = ci
     for f in ("fft2d_plan", "fft2d_plan_batched", "fft2d_exec", "fft2d_exec_pass", "fft2d_exec_pass_timed",
               "fft2d_exec_pass_ablated",
               "fft2d_exec_batched", "fft2d_backward",
-              "fft2d_destroy", "fft2d_plan_describe", "fft2d_plan_twiddles", "fft2d_exec_noalloc"):
+              "fft2d_destroy", "fft2d_plan_describe", "fft2d_plan_twiddles", "fft2d_exec_noalloc",
+              "fft2d_probe_dft16"):
         getattr(lib, f).restype = ci
     return lib
 
@@ -186,6 +188,16 @@ def fft2d_exec_noalloc(batch: int, rows: int, cols: int, in_ptr: int, out_ptr: i
 
 
 NOALLOC_WORK_BYTES = 64 * 1024 * 1024
+
+DFT16_BUTTERFLY = 0
+DFT16_MFMA = 1
+
+
+def fft2d_probe_dft16(method: int, in_ptr: int, out_ptr: int, count: int, reps: int, start_event: int = 0,
+                      stop_event: int = 0, stream: int = 0) -> None:
+    """count 16-point vectors, (Pi F / 4)^reps applied in registers by butterflies or MFMA (rate probe)."""
+    _check(lib.fft2d_probe_dft16(int(method), in_ptr, out_ptr, int(count), int(reps), start_event or None,
+                                 stop_event or None, stream), "fft2d_probe_dft16")
 
 
 def fft2d_destroy(plan: int) -> None:

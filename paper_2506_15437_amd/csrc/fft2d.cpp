@@ -142,6 +142,8 @@ struct fft2d_plan_s {
 
 namespace fft2d {
 
+fft2d_status report_error(fft2d_status st, const std::string& detail) { return fail(st, detail); }
+
 void fill_twiddles(const PassKernel& k, float2* tab) {
   // Pass p >= 1, radix R, Ns = product of earlier radices: entry (r, k) is
   // exp(-2 pi i k r / (Ns R)) for r in [1, R), k in [0, Ns). The exponent

@@ -5,6 +5,9 @@
 #include <hip/hip_runtime.h>
 #include <cstddef>
 #include <cstdint>
+#include <string>
+
+#include "fft2d.h"
 
 namespace fft2d {
 
@@ -95,6 +98,9 @@ inline int pass_blocks(const PassKernel& k, int64_t nvec) { return (int)((nvec +
 // rounded once to FP32. Layout: passes in order, within a pass r-major.
 size_t twiddle_count(const PassKernel& k);
 void fill_twiddles(const PassKernel& k, float2* host_table);
+
+// Record `detail` as this host thread's fft2d_last_error() and return `st`.
+fft2d_status report_error(fft2d_status st, const std::string& detail);
 
 // Scaled copy for 1x1 grids (and the trivial dimension): out[i] = in[i]*scale.
 hipError_t launch_scale_copy(const float2* in, float2* out, int64_t n, float scale, hipStream_t s);

@@ -16,7 +16,7 @@ HEADER = os.path.join(ROOT, "include", "fft2d.h")
 def _declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(fft2d_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(fft2d_[a-z0-9_]+)\s*\(", text)))
 
 
 @pytest.fixture(scope="module")
@@ -147,3 +147,14 @@ def test_noalloc_rejects_bad_arguments_before_touching_the_gpu(L):
     assert f(1, 8, 8, 12, 1024, -1, None) == 4
     assert f(1, 64, 64, 16, 24, -1, None) == 9
     assert "overlap" in L.last_error()
+
+
+def test_dft16_probe_rejects_bad_arguments_before_touching_the_gpu(L):
+    f = L.lib.fft2d_probe_dft16
+    assert f(2, 16, 8192, 64, 8, None, None, None) == 3
+    assert f(0, None, 8192, 64, 8, None, None, None) == 1
+    assert f(0, 16, 8192, 64, 8, 16, None, None) == 1
+    for count, reps in ((0, 8), (63, 8), (96, 8), (64, 0), (64, 12), (64, 8192), (1 << 27, 8)):
+        assert f(1, 16, 1 << 40, count, reps, None, None, None) == 2, (count, reps)
+    assert f(1, 12, 1 << 40, 64, 8, None, None, None) == 4
+    assert f(1, 16, 24, 64, 8, None, None, None) == 9
