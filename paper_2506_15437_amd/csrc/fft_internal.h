@@ -40,6 +40,7 @@ struct PassArgs {
   int64_t m2;         // row pass with combine: M2 = M / M1
   float scale;        // multiplies every output point
   int nblocks;        // grid size (for the XCD-aware block remap)
+  int remap;          // column mode: 1 = XCD-contiguous tile order (xcd_remap), 0 = launch order
 };
 
 // One compiled pass kernel: a length-L FFT with a fixed radix schedule,

@@ -30,9 +30,10 @@
 //
 // Column mode: a workgroup owns C adjacent columns; lanes run over the
 // columns first, so each load/store instruction touches rows of C*8 bytes.
-// Column workgroups are remapped so that each of the 8 XCDs (each with its own
-// L2) works through a contiguous range of column tiles; neighbouring tiles
-// share cache lines and are then served by the same L2.
+// Where C*8 is less than a 128-byte line, column workgroups are remapped so
+// that each of the 8 XCDs (each with its own L2) works through a contiguous
+// range of column tiles: neighbouring tiles share cache lines and are then
+// served by the same L2 (PassArgs::remap; the plan decides).
 #pragma once
 
 #include "fft_internal.h"
@@ -446,7 +447,7 @@ template <class K, int DIR, bool NT = false, int WPE = 1, int SB = 0, int MODE =
 __global__ __launch_bounds__(K::THREADS) __attribute__((amdgpu_waves_per_eu(WPE))) void pass_kernel(PassArgs a) {
   static_assert(K::valid(), "invalid pass configuration");
   __shared__ float2 lds[K::LDS_ELEMS];
-  const int w = K::COL ? xcd_remap(blockIdx.x, a.nblocks) : (int)blockIdx.x;
+  const int w = (K::COL && a.remap) ? xcd_remap(blockIdx.x, a.nblocks) : (int)blockIdx.x;
   TileIO io;
   io.scale = a.scale;
   fft_tile<K, DIR, NT ? kAuxNontemporal : 0, SB, MODE>(a, w, lds, io);
