@@ -173,24 +173,42 @@ def summarize_counters(*run_dirs, roles=ROUND_TRIP_ROLES):
 STATS_PROFILE = os.path.join(ROOT, "profiles", "kernel_stats_fft2d_4096x4096_roundtrip.txt")
 
 
-def summarize_stats(stats_dir):
+def summarize_stats(stats_dir, timed=0):
     """The rows of a rocprofv3 --kernel-trace --stats run (kernel_stats.csv),
-    after the hash of the plain path's sources they were taken from."""
+    after the hash of the plain path's sources they were taken from; with
+    timed = K, also each library pass kernel's mean duration over its last K
+    dispatches (from the kernel trace): the launches of the bench's timed
+    region, which come last in a run."""
     import csv
     with open(os.path.join(stats_dir, "run_kernel_stats.csv"), newline="") as fh:
         rows = list(csv.DictReader(fh))
-    out = ["source_hash = %s" % kernel_source_hash(), "calls  avg_us   min_us   max_us   total_%  kernel"]
+    last = {}
+    if timed:
+        with open(os.path.join(stats_dir, "run_kernel_trace.csv"), newline="") as fh:
+            trace = list(csv.DictReader(fh))
+        by_name = {}
+        for r in trace:
+            if kernel_role(r["Kernel_Name"]) is not None:
+                by_name.setdefault(r["Kernel_Name"], []).append(r)
+        for name, rs in by_name.items():
+            rs.sort(key=lambda r: int(r["Dispatch_Id"]))
+            d = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in rs[-timed:]]
+            last[name] = float(np.mean(d))
+    out = ["source_hash = %s" % kernel_source_hash(),
+           "calls  avg_us   min_us   max_us   total_%%  last%d_us  kernel" % timed]
     for r in rows:
-        out.append("%5s %8.2f %8.2f %8.2f %8.2f  %s" % (r["Calls"], float(r["AverageNs"]) / 1e3,
-                                                      float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3,
-                                                      float(r["Percentage"]), r["Name"]))
+        lt = ("%9.2f" % last[r["Name"]]) if r["Name"] in last else "        -"
+        out.append("%5s %8.2f %8.2f %8.2f %8.2f %s  %s" % (r["Calls"], float(r["AverageNs"]) / 1e3,
+                                                          float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3,
+                                                          float(r["Percentage"]), lt, r["Name"]))
     return "\n".join(out)
 
 
 def rocprof_roofline(pass_name, pass_bytes):
-    """The dominant pass's average duration in the committed rocprofv3 kernel
-    statistics of the round trip (the same bench command under rocprofv3), as
-    a roofline fraction; None when the summary is missing or was taken from
+    """The dominant pass's mean duration over the timed region's launches in
+    the committed rocprofv3 kernel trace of the round trip (the same bench
+    command under rocprofv3), as a roofline fraction, beside its mean over all
+    launches of that run; None when the summary is missing or was taken from
     other kernel sources."""
     try:
         with open(STATS_PROFILE) as fh:
@@ -202,11 +220,12 @@ def rocprof_roofline(pass_name, pass_bytes):
         return None
     want = ROUND_TRIP_ROLES[pass_name]
     for l in lines:
-        f = l.split(None, 5)
-        if len(f) == 6 and f[0].isdigit() and kernel_role(f[5]) == want:
-            avg_us = float(f[1])
-            return {"avg_us": avg_us, "calls": int(f[0]), "achieved": round(pass_bytes / (avg_us * 1e-6) / 1e9, 1),
-                    "frac": round(pass_bytes / (avg_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
+        f = l.split(None, 6)
+        if len(f) == 7 and f[0].isdigit() and kernel_role(f[6]) == want and f[5] != "-":
+            timed_us, all_us = float(f[5]), float(f[1])
+            return {"timed_avg_us": timed_us, "all_launches_avg_us": all_us, "calls": int(f[0]),
+                    "achieved": round(pass_bytes / (timed_us * 1e-6) / 1e9, 1),
+                    "frac": round(pass_bytes / (timed_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
     return None
 
 
@@ -412,36 +431,44 @@ def time_configs(F, torch, iters):
 
 
 def only_config(F, torch, name, steps, warmup):
-    """One configuration's forward transform, `warmup` + `steps` times back to
-    back (for rocprofv3: its kernel statistics then hold that configuration's
-    passes only), then `steps` times pass by pass with events bound to each
-    launch; prints one JSON line with the per-pass mean durations."""
+    """One configuration's forward transform alone, for rocprofv3 (its kernel
+    statistics then hold that configuration's passes only), under the same
+    protocol as the per-pass figures of the default run (time_passes): every
+    transform preceded by a 1 GiB read. `warmup` + `steps` transforms by
+    fft2d_exec, then `steps` pass by pass with events bound to each launch;
+    prints one JSON line with the per-pass mean durations."""
     import synth
     batch, rows, cols, seed = ONLY[name]
     shape = (batch, rows, cols) if batch > 1 else (rows, cols)
     x = torch.from_numpy(synth.complex_grid(seed, shape)).to("cuda")
     y = torch.empty_like(x)
+    scratch = torch.empty(SCRATCH_FLOATS, dtype=torch.float32, device="cuda")
     plan = F.get_plan(batch, rows, cols, x.device)
     stream = torch.cuda.current_stream()
     sh = int(stream.cuda_stream)
     for _ in range(warmup):
+        scratch.sum()
         F.fft2d_exec(plan.handle, x.data_ptr(), y.data_ptr(), F.FORWARD, sh)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for a, b in ev:
+        scratch.sum()
+        a.record(stream)
         F.fft2d_exec(plan.handle, x.data_ptr(), y.data_ptr(), F.FORWARD, sh)
+        b.record(stream)
     torch.cuda.synchronize()
-    wall = (time.perf_counter() - t0) / steps * 1e3
+    per_transform = float(np.mean([a.elapsed_time(b) for a, b in ev]))
     whole = " grid[" in plan.describe()
     passes = [] if whole else [p for p, n in ((0, cols), (1, rows)) if n > 1]
-    ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in passes]
-          for _ in range(steps)]
-    for row in ev:
+    pev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in passes]
+           for _ in range(steps)]
+    for row in pev:
         for a, b in row:
             a.record(stream)
             b.record(stream)
     torch.cuda.synchronize()
-    for row in ev:
+    for row in pev:
+        scratch.sum()
         for pidx, (a, b) in zip(passes, row):
             F.fft2d_exec_pass_timed(plan.handle, x.data_ptr(), y.data_ptr(), F.FORWARD, pidx, a.cuda_event,
                                     b.cuda_event, sh)
@@ -449,10 +476,13 @@ def only_config(F, torch, name, steps, warmup):
     nbytes = BYTES_PER_POINT_PER_PASS * batch * rows * cols
     per = {}
     for i, pidx in enumerate(passes):
-        t = float(np.mean([row[i][0].elapsed_time(row[i][1]) for row in ev]))
+        t = float(np.mean([row[i][0].elapsed_time(row[i][1]) for row in pev]))
         per["row" if pidx == 0 else "col"] = {"ms": round(t, 5), "frac": _frac(nbytes, t)}
-    print(json.dumps({"only": name, "steps": steps, "warmup": warmup, "ms_per_transform": round(wall, 5),
-                      "passes": per, "plan": plan.describe()}), flush=True)
+    npass = 1 if whole else len(passes)
+    print(json.dumps({"only": name, "steps": steps, "warmup": warmup, "protocol": "1 GiB read before each transform",
+                      "ms_per_transform": round(per_transform, 5),
+                      "frac": _frac(npass * nbytes, per_transform), "passes": per, "plan": plan.describe()}),
+          flush=True)
 
 
 def device_copy_gbps(torch, iters=20):
@@ -822,19 +852,22 @@ def main():
                     help="print the mean of every counter per pass from rocprofv3 --pmc output folders, then exit")
     ap.add_argument("--summarize-stats", metavar="DIR",
                     help="print the kernel rows of a rocprofv3 --kernel-trace --stats output folder, then exit")
-    ap.add_argument("--profiled", default="4096x4096",
-                    help="for --summarize-*: the workload profiled: 4096x4096 (the round trip) or an --only name")
+    ap.add_argument("--timed", type=int, default=0,
+                    help="for --summarize-stats: also average each pass kernel's last TIMED dispatches")
+    ap.add_argument("--profiled", default="roundtrip", choices=["roundtrip"] + sorted(ONLY),
+                    help="for --summarize-*: the workload profiled: the 4096x4096 round trip (default) or the "
+                         "forward transform of an --only configuration")
     args = ap.parse_args()
-    roles = ROUND_TRIP_ROLES if args.profiled == "4096x4096" else FORWARD_ROLES
+    roles = ROUND_TRIP_ROLES if args.profiled == "roundtrip" else FORWARD_ROLES
     if args.summarize_traffic:
-        b, r_, c_, _ = ONLY[args.profiled]
+        b, r_, c_, _ = ONLY["4096x4096" if args.profiled == "roundtrip" else args.profiled]
         print(summarize_traffic(*args.summarize_traffic, points=b * r_ * c_, roles=roles))
         return
     if args.summarize_counters:
         print(summarize_counters(*args.summarize_counters, roles=roles))
         return
     if args.summarize_stats:
-        print(summarize_stats(args.summarize_stats))
+        print(summarize_stats(args.summarize_stats, args.timed))
         return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
