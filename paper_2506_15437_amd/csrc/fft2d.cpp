@@ -96,6 +96,17 @@ bool use_wide_columns() {
   return !(env && std::strcmp(env, "narrow") == 0);
 }
 
+// Whether a split plan's column pass uses a two-stage radix schedule (one LDS
+// exchange: 32 x 32 for 1024-point columns, 64 x 32 for 2048-point columns)
+// where there is one, rather than three stages (two exchanges). Measured on
+// MI355X, column pass, forward, 1 GiB read before each transform: 8192^2
+// 275.2 against 294.4 us, 16384 x 2048 109.3 against 119.1 us, 4096^2 45.5
+// against 48.2 us. FFT2D_COLUMN_STAGES=two|classic overrides (default two).
+bool use_two_stage_columns() {
+  const char* env = std::getenv("FFT2D_COLUMN_STAGES");
+  return !(env && std::strcmp(env, "classic") == 0);
+}
+
 // Whether a plain pass over `vectors` rows or columns, whose default kernel
 // takes `c` of them per tile, uses the narrower-tile kernel: when the default
 // would give at most one tile per CU (rows; one 1024^2 grid has 256 row tiles
@@ -123,6 +134,18 @@ int use_xcd_remap(const PassKernel& k) {
   if (env && std::strcmp(env, "0") == 0) return 0;
   if (env && std::strcmp(env, "1") == 0) return 1;
   return k.C * 8 < 128 ? 1 : 0;
+}
+
+// Whether a split plan's row pass runs the combine kernel whose last FFT stage
+// works across the workgroup's rows (rowx_kernel: one LDS exchange fewer)
+// rather than the one with a separate combine exchange (rowc_kernel), where
+// both exist for the row length. Measured on MI355X, row pass, forward, 1 GiB
+// read before each transform: 8192^2 224.9 against 246.2 us, 16384 x 2048
+// 107.4 against 112.4 us, 8 x 2048^2 102.2 against 109.1 us, 4096^2 55.4
+// against 57.2 us. FFT2D_COMBINE=xrow|classic overrides (default xrow).
+bool use_cross_row_combine() {
+  const char* env = std::getenv("FFT2D_COMBINE");
+  return !(env && std::strcmp(env, "classic") == 0);
 }
 
 // Same FFT length and radix sequence (hence the same twiddle table).
@@ -427,8 +450,8 @@ fft2d_status select_kernels(fft2d_plan_s* p, int64_t batch, int64_t rows, int64_
   p->m2 = rows / p->m1;
 
   if (p->m1 > 1) {
-    p->row_k = find_combine_kernel((int)cols, (int)p->m1);
-    p->col_k = find_split_column_kernel((int)p->m2, use_wide_columns());
+    p->row_k = find_combine_kernel((int)cols, (int)p->m1, use_cross_row_combine());
+    p->col_k = find_split_column_kernel((int)p->m2, use_wide_columns(), use_two_stage_columns());
     if (!p->col_k) p->col_k = find_pass_kernel((int)p->m2, true);
   } else {
     if (cols > 1) p->row_k = find_pass_kernel((int)cols, false);
@@ -756,7 +779,7 @@ fft2d_status fft2d_plan_describe(fft2d_plan_t plan, char* buf, int64_t buflen) {
                             " lds=" + std::to_string(plan->grid_k->lds_bytes) + "]"
                       : std::string()) +
         " row[" + desc(plan->row_k) +
-        (plan->m1 > 1 ? " combine" : "") + "] col[" + desc(plan->col_k) + (plan->col_remap ? " xcd-remap" : "") +
+        (plan->m1 > 1 ? (plan->row_k->xrow ? " combine xrow" : " combine") : "") + "] col[" + desc(plan->col_k) + (plan->col_remap ? " xcd-remap" : "") +
         "]";
   } else {
     d = describe_batched(plan->batched);

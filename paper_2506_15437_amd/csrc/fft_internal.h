@@ -53,6 +53,7 @@ struct PassKernel {
   int L, E, T, C, Q, threads;
   int colmode;
   int combine;  // row pass with an M1 = C point combine across its rows (split column transform)
+  int xrow;     // combine kernel whose last FFT stage runs across its rows (one LDS exchange fewer)
   int wpe;  // minimum waves per SIMD the kernel was compiled for
   int nt;   // nontemporal input loads
   int npass;
@@ -80,11 +81,15 @@ const PassKernel* find_pass_kernel(int L, bool colmode);
 // Pass of length L with narrower tiles, for passes with few tiles (nullptr
 // if none).
 const PassKernel* find_few_tiles_kernel(int L, bool colmode);
-// Row pass with an M1-point combine across M1 rows of length L (nullptr if none).
-const PassKernel* find_combine_kernel(int L, int m1);
-// Column pass for the length-M2 columns of a split transform; `wide` prefers
-// the 64-points-per-thread variant where there is one (large grids).
-const PassKernel* find_split_column_kernel(int L, bool wide = false);
+// Row pass with an M1-point combine across M1 rows of length L (nullptr if
+// none); `cross_row` prefers the variant whose last stage runs across the rows
+// (rowx_kernel) where both exist.
+const PassKernel* find_combine_kernel(int L, int m1, bool cross_row = true);
+// Column pass for the length-M2 columns of a split transform; `two_stage`
+// prefers a two-stage radix schedule (one LDS exchange) where there is one,
+// then `wide` the 64-points-per-thread variant where there is one (large
+// grids).
+const PassKernel* find_split_column_kernel(int L, bool wide = false, bool two_stage = false);
 // Whole-grid kernel for rows x cols grids (nullptr if none).
 const GridKernel* find_grid_kernel(int rows, int cols);
 // All compiled variants for a length (for the autotuner); returns the count.

@@ -34,16 +34,25 @@ const PassKernel* find_few_tiles_kernel(int L, bool colmode) {
   return nullptr;
 }
 
-const PassKernel* find_combine_kernel(int L, int m1) {
+const PassKernel* find_combine_kernel(int L, int m1, bool cross_row) {
   int n = 0;
   const PassKernel* tab = combine_kernel_table(&n);
-  for (int i = 0; i < n; ++i)
-    if (tab[i].L == L && tab[i].C == m1) return &tab[i];
-  return nullptr;
+  const PassKernel* any = nullptr;
+  for (int i = 0; i < n; ++i) {
+    if (tab[i].L != L || tab[i].C != m1) continue;
+    if ((tab[i].xrow != 0) == cross_row) return &tab[i];
+    if (!any) any = &tab[i];
+  }
+  return any;
 }
 
-const PassKernel* find_split_column_kernel(int L, bool wide) {
+const PassKernel* find_split_column_kernel(int L, bool wide, bool two_stage) {
   int n = 0;
+  if (two_stage) {
+    const PassKernel* tab = split_col_two_stage_kernel_table(&n);
+    for (int i = 0; i < n; ++i)
+      if (tab[i].L == L && (wide || tab[i].E <= 32)) return &tab[i];
+  }
   if (wide) {
     const PassKernel* tab = split_col_wide_kernel_table(&n);
     for (int i = 0; i < n; ++i)

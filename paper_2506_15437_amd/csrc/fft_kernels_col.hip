@@ -31,12 +31,12 @@ using C512F = Cfg<512, 16, 8, 1, true, 16, 16, 2>;     // 256 threads, 8 columns
 using C1024F = Cfg<1024, 16, 4, 1, true, 16, 16, 4>;   // 256 threads, 4 columns
 using C2048F = Cfg<2048, 16, 4, 1, true, 16, 16, 8>;   // 512 threads, 4 columns
 const PassKernel kColFewKernels[] = {
-    describe<C512F>(), describe<C1024F, false, 1, false, true>(), describe<C2048F>(),
+    describe<C512F>(), describe<C1024F, kKindPass, 1, false, true>(), describe<C2048F>(),
 };
 
 const PassKernel kColKernels[] = {
     describe<C2>(),   describe<C4>(),   describe<C8>(),    describe<C16>(),   describe<C32>(),
-    describe<C64>(),  describe<C128>(), describe<C256, false, 1, false, true>(),  describe<C512>(),  describe<C1024>(),
+    describe<C64>(),  describe<C128>(), describe<C256, kKindPass, 1, false, true>(),  describe<C512>(),  describe<C1024>(),
     describe<C2048>(), describe<C4096>(), describe<C8192>(), describe<C16384>(),
 };
 

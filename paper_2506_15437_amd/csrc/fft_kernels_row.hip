@@ -29,13 +29,13 @@ using R16384 = Cfg<16384, 64, 1, 2, false, 16, 16, 16, 4>;  // 256 threads, two 
 // (e.g. one 1024 x 1024 grid: 256 tiles of 4 rows, or 1024 of one).
 using R1024F = Cfg<1024, 16, 1, 1, false, 16, 16, 4>;
 const PassKernel kRowFewKernels[] = {
-    describe<R1024F, false, 1, true, true>(),
+    describe<R1024F, kKindPass, 1, true, true>(),
 };
 
 const PassKernel kRowKernels[] = {
     describe<R2>(),   describe<R4>(),   describe<R8>(),    describe<R16>(),   describe<R32>(),
     describe<R64>(),  describe<R128>(), describe<R256>(),  describe<R512>(),  describe<R1024>(),
-    describe<R2048>(), describe<R4096>(), describe<R8192>(), describe<R16384, false, 1, true, true>(),
+    describe<R2048>(), describe<R4096>(), describe<R8192>(), describe<R16384, kKindPass, 1, true, true>(),
 };
 
 }  // namespace

@@ -27,14 +27,27 @@ using S1024 = Cfg<1024, 32, 16, 2, true, 16, 16, 4>;
 using S2048 = Cfg<2048, 32, 16, 2, true, 16, 16, 8>;
 using S4096 = Cfg<4096, 32, 8, 2, true, 16, 16, 16>;
 
+// The same with the row FFT's last stage across the M1 rows (rowx_kernel): the
+// last radix times M1 is the points per thread, and the combine DFT runs in
+// registers on that stage's outputs, so there is no separate combine exchange.
+using RX8192x4 = Cfg<8192, 32, 4, 2, false, 32, 32, 8>;
+using RX16384x2 = Cfg<16384, 32, 2, 2, false, 32, 32, 16>;
+using RX4096x4 = Cfg<4096, 32, 4, 2, false, 16, 32, 8>;
+using RX2048x8 = Cfg<2048, 32, 8, 2, false, 16, 32, 4>;
+using RX1024x16 = Cfg<1024, 32, 16, 2, false, 16, 32, 2>;
+
 const PassKernel kCombineKernels[] = {
-    describe<RC8192x2, true, 4>(), describe<RC8192x4, true, 1, true, true>(), describe<RC16384x2, true, 1>(),
-    describe<RC4096x4, true, 4, true, true>(),
-    describe<RC2048x8, true, 4, true, true>(),
-    describe<RC1024x16, true, 4>(),
+    describe<RC8192x2, kKindCombine, 4>(), describe<RC8192x4, kKindCombine, 1, true, true>(),
+    describe<RC16384x2, kKindCombine, 1>(),
+    describe<RC4096x4, kKindCombine, 4, true, true>(),
+    describe<RC2048x8, kKindCombine, 4, true, true>(),
+    describe<RC1024x16, kKindCombine, 4>(),
+    describe<RX8192x4, kKindCrossRow, 1, true, true>(), describe<RX16384x2, kKindCrossRow, 1>(),
+    describe<RX4096x4, kKindCrossRow, 4, true, true>(), describe<RX2048x8, kKindCrossRow, 4, true, true>(),
+    describe<RX1024x16, kKindCrossRow, 4>(),
 };
 const PassKernel kSplitColKernels[] = {
-    describe<S512>(), describe<S1024, false, 1, false, true>(), describe<S2048>(), describe<S4096>(),
+    describe<S512>(), describe<S1024, kKindPass, 1, false, true>(), describe<S2048>(), describe<S4096>(),
 };
 // Column passes with 64 points per thread (512 threads) for split transforms
 // whose data come from HBM rather than the MALL (large grids): more loads in
@@ -43,7 +56,15 @@ using S2048W = Cfg<2048, 64, 16, 2, true, 16, 16, 8>;
 using S4096W = Cfg<4096, 64, 8, 4, true, 16, 16, 16>;
 using S8192W = Cfg<8192, 64, 4, 2, true, 16, 16, 32>;
 const PassKernel kSplitColWideKernels[] = {
-    describe<S2048W, false, 1, false, true>(), describe<S4096W>(), describe<S8192W>(),
+    describe<S2048W, kKindPass, 1, false, true>(), describe<S4096W>(), describe<S8192W>(),
+};
+// Two-stage schedules (one LDS exchange): radix 32 x 32 for 1024-point columns
+// (32 points per thread), radix 64 x 32 for 2048-point columns (64 points per
+// thread).
+using S1024B = Cfg<1024, 32, 16, 2, true, 32, 32>;
+using S2048B = Cfg<2048, 64, 16, 2, true, 64, 32>;
+const PassKernel kSplitColTwoStageKernels[] = {
+    describe<S1024B, kKindPass, 1, false, true>(), describe<S2048B, kKindPass, 1, false, true>(),
 };
 
 }  // namespace
@@ -56,6 +77,11 @@ const PassKernel* combine_kernel_table(int* count) {
 const PassKernel* split_col_kernel_table(int* count) {
   *count = (int)(sizeof(kSplitColKernels) / sizeof(kSplitColKernels[0]));
   return kSplitColKernels;
+}
+
+const PassKernel* split_col_two_stage_kernel_table(int* count) {
+  *count = (int)(sizeof(kSplitColTwoStageKernels) / sizeof(kSplitColTwoStageKernels[0]));
+  return kSplitColTwoStageKernels;
 }
 
 const PassKernel* split_col_wide_kernel_table(int* count) {

@@ -253,7 +253,19 @@ struct Cfg {
     for (int q = 1; q < p; ++q) o += ns(q) * (radix(q) - 1);
     return o;
   }
-  static constexpr int pad(int e) { return e + (e >> 4); }
+  static constexpr int max_exchanged_radix() {  // largest radix of a pass followed by an LDS exchange
+    int m = 1;
+    for (int p = 0; p + 1 < P; ++p) m = radix(p) > m ? radix(p) : m;
+    return m;
+  }
+  // LDS rows get one padding slot per 2^PADSHIFT points: every 16 for radix-16
+  // write patterns; every 32 where a pass followed by an exchange has radix 32
+  // or more (its lanes write slots 32 apart: one pad per 16 would put lanes k
+  // and k + 16 on the same banks), except for row vectors shorter than 32
+  // threads, whose rows are offset from each other already (ROWSTRIDE).
+  static constexpr int PADSHIFT = (max_exchanged_radix() >= 32 && (COL || T >= 32)) ? 5 : 4;
+  static constexpr int PADSPAN = 1 << PADSHIFT;
+  static constexpr int pad(int e) { return e + (e >> PADSHIFT); }
   static constexpr int LQP = pad(LQ - 1) + 1;
   // Row mode: consecutive vectors of one wave start T banks-pairs apart.
   static constexpr int ROWSTRIDE = (T >= 32) ? LQP : (LQP + T);
@@ -263,10 +275,19 @@ struct Cfg {
     if constexpr (COL) return pad(e) * C + c;
     else return c * ROWSTRIDE + pad(e);
   }
-  // Slot distance of point e0 + x from point e0 when the low four bits of e0
-  // and of x never carry into bit 4 (then pad(e0 + x) = pad(e0) + pad(x)), so
-  // that an address is a per-thread base plus a compile-time offset.
+  // Slot distance of point e0 + x from point e0 when the low PADSHIFT bits of
+  // e0 and of x never carry into bit PADSHIFT (then pad(e0 + x) = pad(e0) +
+  // pad(x)), so that an address is a per-thread base plus a compile-time
+  // offset.
   static constexpr int lds_delta(int x) { return COL ? pad(x) * C : pad(x); }
+
+  // Exchange rounds. Output s of butterfly b of pass p goes to position
+  // (b div Ns) Ns R + (b mod Ns) + s Ns, inside a block of Ns R positions; with
+  // Ns R <= L/Q every butterfly's outputs fall in one round, round b div
+  // (L/(Q R)). Where a thread has at least Q butterflies per pass (E/R a
+  // multiple of Q) that round depends on the butterfly's index i only
+  // (by_index); otherwise (fewer butterflies than rounds) also on the thread.
+  static constexpr bool by_index(int p) { return (E / radix(p)) % Q == 0; }
 
   static constexpr bool valid() {
     int prod = 1;
@@ -277,13 +298,20 @@ struct Cfg {
     if (prod != L || L % E != 0 || THREADS > 1024 || THREADS % 64 != 0) return false;
     if (Q > 1) {
       for (int p = 0; p + 1 < P; ++p) {
-        if ((E / radix(p)) % Q != 0) return false;  // whole butterflies per round
-        if (ns(p) > T) return false;                // destinations of one butterfly stay in one round
+        if (by_index(p)) {
+          if (ns(p) > T) return false;  // destinations of one butterfly stay in one round
+        } else if (ns(p) * radix(p) > LQ) {
+          return false;
+        }
       }
     }
-    return LDS_ELEMS * 8 <= 160 * 1024;
+    return E % Q == 0 && LDS_ELEMS * 8 <= 160 * 1024;
   }
 };
+
+constexpr int kKindPass = 0;
+constexpr int kKindCombine = 1;
+constexpr int kKindCrossRow = 2;
 
 __device__ __forceinline__ int xcd_remap(int b, int nb) {
   // Consecutive workgroup ids are dispatched round-robin over the 8 XCDs; give
@@ -299,7 +327,12 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
 // same order) and drops its arithmetic (twiddle loads, multiplications and the
 // butterflies): the "compute off" variant used to measure the pass's
 // data-movement ceiling.
-template <class K, int DIR, int p, int SB = 0, bool ARITH = true>
+// RD selects what each thread reads back after the exchange: 0, the points
+// tt + T j of its own vector (the next pass's inputs); 1 (row mode, last
+// exchange of a row pass with cross-row last stage, see rowx_tile), for every
+// row c' of the workgroup the points t + r L/RL (r < RL, RL = the last radix)
+// into d[c' RL + r], t the thread's index in the workgroup.
+template <class K, int DIR, int p, int SB = 0, bool ARITH = true, int RD = 0>
 __device__ __forceinline__ void run_pass(float2 (&d)[K::E], float2* lds, int tt, int c, const Buf& tw) {
   constexpr int R = K::radix(p);
   constexpr int Ns = K::ns(p);
@@ -334,36 +367,59 @@ __device__ __forceinline__ void run_pass(float2 (&d)[K::E], float2* lds, int tt,
     if constexpr (SB != 0) __builtin_amdgcn_sched_barrier(0);
   });
   if constexpr (!last) {
-    constexpr int NBQ = NB / K::Q;
     constexpr int EQ = K::E / K::Q;
-    // reads: point tt + T j' (j' < EQ) of the round, tt < T, so the slot is
-    // lds_index(c, tt) + lds_delta(T j')
-    const int rbase = K::lds_index(c, tt);
+    // writes of butterfly i (positions relative to round h's first point)
+    auto put = [&](auto I, int h) {
+      constexpr int i = decltype(I)::value;
+      const int b = tt + K::T * i;
+      const int dst = (b / Ns) * Ns * R + (b & (Ns - 1)) - h * K::LQ;
+      if constexpr (Ns * R >= K::PADSPAN) {
+        // dst's low PADSHIFT bits are b mod Ns (< Ns), and s Ns adds multiples of Ns
+        const int wbase = K::lds_index(c, dst);
+        static_for<0, R>([&](auto S) {
+          constexpr int s = decltype(S)::value;
+          lds[wbase + K::lds_delta(s * Ns)] = o[i * R + s];
+        });
+      } else {
+        static_for<0, R>([&](auto S) {
+          constexpr int s = decltype(S)::value;
+          lds[K::lds_index(c, dst + s * Ns)] = o[i * R + s];
+        });
+      }
+    };
     static_for<0, K::Q>([&](auto H) {
       constexpr int h = decltype(H)::value;
-      static_for<0, NBQ>([&](auto I) {
-        constexpr int i = h * NBQ + decltype(I)::value;
-        const int b = tt + K::T * i;
-        const int dst = (b / Ns) * Ns * R + (b & (Ns - 1)) - h * K::LQ;
-        if constexpr (Ns * R >= 16) {
-          // dst's low four bits are b mod Ns (< Ns), and s Ns adds multiples of Ns
-          const int wbase = K::lds_index(c, dst);
-          static_for<0, R>([&](auto S) {
-            constexpr int s = decltype(S)::value;
-            lds[wbase + K::lds_delta(s * Ns)] = o[i * R + s];
-          });
-        } else {
-          static_for<0, R>([&](auto S) {
-            constexpr int s = decltype(S)::value;
-            lds[K::lds_index(c, dst + s * Ns)] = o[i * R + s];
-          });
-        }
-      });
+      if constexpr (K::by_index(p)) {
+        constexpr int NBQ = NB / K::Q;
+        static_for<h * NBQ, (h + 1) * NBQ>([&](auto I) { put(I, h); });
+      } else {
+        // fewer butterflies than rounds: butterfly b's round is b div (L/(Q R))
+        static_for<0, NB>([&](auto I) {
+          if ((tt + K::T * decltype(I)::value) / (K::LQ / R) == h) put(I, h);
+        });
+      }
       __syncthreads();
-      static_for<0, EQ>([&](auto J) {
-        constexpr int jj = decltype(J)::value;
-        d[h * EQ + jj] = lds[rbase + K::lds_delta(K::T * jj)];
-      });
+      if constexpr (RD == 0) {
+        // reads: point tt + T j' (j' < EQ) of the round, tt < T, so the slot is
+        // lds_index(c, tt) + lds_delta(T j')
+        const int rbase = K::lds_index(c, tt);
+        static_for<0, EQ>([&](auto J) {
+          constexpr int jj = decltype(J)::value;
+          d[h * EQ + jj] = lds[rbase + K::lds_delta(K::T * jj)];
+        });
+      } else {
+        constexpr int RL = K::radix(K::P - 1);
+        constexpr int RLQ = RL / K::Q;  // last-stage inputs r of round h: h RLQ <= r < (h + 1) RLQ
+        constexpr int SPAN = K::L / RL;  // = THREADS, a multiple of PADSPAN
+        const int t = (int)threadIdx.x;
+        static_for<0, K::C>([&](auto Cc) {
+          constexpr int cr = decltype(Cc)::value;
+          static_for<0, RLQ>([&](auto Rq) {
+            constexpr int r = h * RLQ + decltype(Rq)::value;
+            d[cr * RL + r] = lds[cr * K::ROWSTRIDE + K::pad(t) + K::pad(decltype(Rq)::value * SPAN)];
+          });
+        });
+      }
       __syncthreads();
     });
   }
@@ -544,6 +600,98 @@ __global__ __launch_bounds__(K::THREADS) __attribute__((amdgpu_waves_per_eu(WPE)
   rowc_tile<K, DIR, NT ? kAuxNontemporal : 0, SB, MODE>(a, blockIdx.x, lds, TileIO{});
 }
 
+// Row pass with combine whose last FFT stage runs across the workgroup's rows
+// (the same result as rowc_tile with one LDS exchange fewer). The length-L
+// row FFT's last stage has radix RL = E / M1 and L / RL = THREADS butterflies
+// per row; its inputs cross the LDS in the exchange after the stage before,
+// and thread t takes butterfly t of every one of the M1 rows (RL points each).
+// The stage's outputs t + s L/RL of the M1 rows are then exactly the points
+// the M1-point combine needs, so the combine DFT and its twiddle W_M^(m2 k1)
+// run in registers and store row k1's points t + s L/RL (coalesced over t).
+// The twiddles of the last stage, W_L^(t r), are the same for every row and
+// loaded once. MODE as for rowc_tile.
+template <class K, int DIR, int AUX = 0, int SB = 0, int MODE = 0>
+__device__ __forceinline__ void rowx_tile(const PassArgs& a, int64_t w, float2* lds, TileIO io) {
+  constexpr int M1 = K::C;
+  constexpr int RL = K::radix(K::P - 1);
+  constexpr int SPAN = K::L / RL;
+  static_assert(K::valid() && !K::COL && M1 >= 2 && K::P > 1, "invalid combine configuration");
+  static_assert(RL * M1 == K::E && SPAN == K::THREADS && RL % K::Q == 0 && SPAN % K::PADSPAN == 0,
+                "the last stage must take one butterfly of every row per thread");
+  const int t = threadIdx.x;
+  const int c = t / K::T;
+  const int tt = t % K::T;
+  const int64_t g = w / a.m2;
+  const int64_t m2 = w - g * a.m2;
+  const int64_t gbase = g * a.m2 * M1 * K::L;
+  const int64_t base = gbase + m2 * K::L;
+  const int64_t obase = gbase + m2 * M1 * K::L;
+  const Buf src(a.in + base, span_bytes(a.total, base));
+  const Buf dst(a.out + obase, span_bytes(a.total, obase));
+  const Buf tw(a.tw, (uint32_t)a.tw_count * 8u);
+  const uint32_t row_bytes = (uint32_t)(a.m2 * K::L) * 8u;  // from row m2 + M2*k to row m2 + M2*(k+1)
+  const uint32_t voff_in = (uint32_t)c * row_bytes + (uint32_t)tt * 8u;
+  float2 d[K::E];
+  static_for<0, K::E>([&](auto J) {
+    constexpr int j = decltype(J)::value;
+    d[j] = src.load<AUX>(voff_in, (uint32_t)(K::T * j) * 8u);
+  });
+  if (io.conj_in) static_for<0, K::E>([&](auto J) { d[decltype(J)::value].y = -d[decltype(J)::value].y; });
+  if constexpr (MODE == 2) {
+    const uint32_t voff_out = (uint32_t)c * (uint32_t)(K::L * 8) + (uint32_t)tt * 8u;
+    static_for<0, K::E>([&](auto J) {
+      constexpr int j = decltype(J)::value;
+      dst.store(d[j], voff_out, (uint32_t)(K::T * j) * 8u);
+    });
+    return;
+  }
+  static_for<0, K::P - 2>([&](auto Pp) { run_pass<K, DIR, decltype(Pp)::value, SB, MODE == 0>(d, lds, tt, c, tw); });
+  run_pass<K, DIR, K::P - 2, SB, MODE == 0, 1>(d, lds, tt, c, tw);
+  float2 wk[M1];
+  if constexpr (MODE == 0) {
+    float2 wl[RL];
+    static_for<1, RL>([&](auto Rr) {
+      constexpr int r = decltype(Rr)::value;
+      float2 v = tw.load((uint32_t)t * 8u, (uint32_t)(K::tw_off(K::P - 1) + (r - 1) * SPAN) * 8u);
+      if constexpr (DIR > 0) v.y = -v.y;
+      wl[r] = v;
+    });
+    static_for<1, M1>([&](auto Kk) {
+      constexpr int k1 = decltype(Kk)::value;
+      float2 w1 = a.twc[m2 * k1];
+      if constexpr (DIR > 0) w1.y = -w1.y;
+      wk[k1] = w1;
+    });
+    static_for<0, M1>([&](auto Cc) {
+      constexpr int cr = decltype(Cc)::value;
+      float2 x[RL];
+      static_for<0, RL>([&](auto Rr) {
+        constexpr int r = decltype(Rr)::value;
+        x[r] = (r == 0) ? d[cr * RL] : cmul(d[cr * RL + r], wl[r]);
+      });
+      dft<RL, DIR>(x);
+      static_for<0, RL>([&](auto S) { d[cr * RL + decltype(S)::value] = x[decltype(S)::value]; });
+    });
+  }
+  static_for<0, RL>([&](auto S) {
+    constexpr int s = decltype(S)::value;
+    float2 z[M1];
+    static_for<0, M1>([&](auto Cc) { z[decltype(Cc)::value] = d[decltype(Cc)::value * RL + s]; });
+    if constexpr (MODE == 0) dft<M1, DIR>(z);
+    static_for<0, M1>([&](auto Kk) {
+      constexpr int k1 = decltype(Kk)::value;
+      dst.store((k1 == 0 || MODE != 0) ? z[k1] : cmul(z[k1], wk[k1]), (uint32_t)t * 8u,
+                (uint32_t)(k1 * K::L + s * SPAN) * 8u);
+    });
+  });
+}
+
+template <class K, int DIR, int WPE = 1, int SB = 0, bool NT = false, int MODE = 0>
+__global__ __launch_bounds__(K::THREADS) __attribute__((amdgpu_waves_per_eu(WPE))) void rowx_kernel(PassArgs a) {
+  __shared__ float2 lds[K::LDS_ELEMS];
+  rowx_tile<K, DIR, NT ? kAuxNontemporal : 0, SB, MODE>(a, blockIdx.x, lds, TileIO{});
+}
+
 // Whole-grid tile: one workgroup computes the complete 2D transform of one
 // M x N grid (M = KC::L rows, N = KR::L columns), reading and writing every
 // point once. Row tiles of KR::C rows are loaded and transformed in turn; each
@@ -659,13 +807,26 @@ hipError_t launch_rowc(const PassArgs& a, int dir, hipStream_t s, hipEvent_t t0,
   return hipGetLastError();
 }
 
+template <class K, int WPE, bool NT>
+hipError_t launch_rowx(const PassArgs& a, int dir, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
+  if (t0 != nullptr || t1 != nullptr)
+    return launch_timed(dir < 0 ? rowx_kernel<K, -1, WPE, 0, NT> : rowx_kernel<K, +1, WPE, 0, NT>, a, K::THREADS,
+                        s, t0, t1);
+  if (dir < 0) hipLaunchKernelGGL((rowx_kernel<K, -1, WPE, 0, NT>), dim3(a.nblocks), dim3(K::THREADS), 0, s, a);
+  else hipLaunchKernelGGL((rowx_kernel<K, +1, WPE, 0, NT>), dim3(a.nblocks), dim3(K::THREADS), 0, s, a);
+  return hipGetLastError();
+}
+
 // Measurement variants (MODE 1: data movement without arithmetic, MODE 2:
 // loads and stores only) of a pass, launched like launch_pass/launch_rowc
 // with the forward sign (events optional).
-template <class K, int WPE, bool NT, bool COMBINE>
+template <class K, int WPE, bool NT, int KIND>
 hipError_t launch_probe(const PassArgs& a, int mode, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
   void (*k)(PassArgs) = nullptr;
-  if constexpr (COMBINE) k = mode == 1 ? rowc_kernel<K, -1, WPE, 0, NT, 1> : rowc_kernel<K, -1, WPE, 0, NT, 2>;
+  if constexpr (KIND == kKindCombine)
+    k = mode == 1 ? rowc_kernel<K, -1, WPE, 0, NT, 1> : rowc_kernel<K, -1, WPE, 0, NT, 2>;
+  else if constexpr (KIND == kKindCrossRow)
+    k = mode == 1 ? rowx_kernel<K, -1, WPE, 0, NT, 1> : rowx_kernel<K, -1, WPE, 0, NT, 2>;
   else k = mode == 1 ? pass_kernel<K, -1, NT, WPE, 0, 1> : pass_kernel<K, -1, NT, WPE, 0, 2>;
   if (t0 != nullptr || t1 != nullptr) return launch_timed(k, a, K::THREADS, s, t0, t1);
   hipLaunchKernelGGL(k, dim3(a.nblocks), dim3(K::THREADS), 0, s, a);
@@ -690,14 +851,18 @@ constexpr PassKernel meta() {
   return k;
 }
 
+// KIND: kKindPass (a plain row or column pass), kKindCombine (row pass with
+// an M1 = C point combine, rowc_kernel) or kKindCrossRow (the same with the
+// last stage across rows, rowx_kernel).
 // WPE: minimum waves per SIMD the compiler must allow (bounds VGPR use).
 // NT: nontemporal loads of the input (row passes read data not reused soon;
 // measured faster from HBM, slower when the data already sits in the MALL).
 // PROBE: also compile the measurement variants (launch_probe).
-template <class K, bool COMBINE = false, int WPE = 1, bool NT = !K::COL, bool PROBE = false>
+template <class K, int KIND = kKindPass, int WPE = 1, bool NT = !K::COL, bool PROBE = false>
 constexpr PassKernel describe() {
   PassKernel k{};
-  k.combine = COMBINE ? K::C : 0;
+  k.combine = KIND != kKindPass ? K::C : 0;
+  k.xrow = KIND == kKindCrossRow ? 1 : 0;
   k.L = K::L;
   k.E = K::E;
   k.T = K::T;
@@ -710,9 +875,10 @@ constexpr PassKernel describe() {
   k.lds_bytes = (size_t)K::LDS_ELEMS * 8;
   k.wpe = WPE;
   k.nt = NT ? 1 : 0;
-  if constexpr (COMBINE) k.launch = &launch_rowc<K, WPE, NT>;
+  if constexpr (KIND == kKindCombine) k.launch = &launch_rowc<K, WPE, NT>;
+  else if constexpr (KIND == kKindCrossRow) k.launch = &launch_rowx<K, WPE, NT>;
   else k.launch = &launch_pass<K, WPE, NT>;
-  if constexpr (PROBE) k.launch_probe = &launch_probe<K, WPE, NT, COMBINE>;
+  if constexpr (PROBE) k.launch_probe = &launch_probe<K, WPE, NT, KIND>;
   return k;
 }
 

@@ -223,13 +223,22 @@ SPLIT_CASES = [(1, (32, 1024), 16), (2, (64, 1024), 16), (1, (256, 2048), 8), (3
                (1, (8192, 2048), 8), (1, (64, 16384), 2), (2, (32, 16384), 2)]
 
 
+@pytest.mark.parametrize("combine", ["xrow", "classic"])
 @pytest.mark.parametrize("batch,shape,m1", SPLIT_CASES, ids=lambda v: str(v))
-def test_split_transform(F, batch, shape, m1, monkeypatch):
-    say("case split batch %d shape %dx%d m1 %d" % ((batch,) + shape + (m1,)))
+def test_split_transform(F, batch, shape, m1, combine, monkeypatch):
+    """Forward, inverse, adjoint and in-place split transforms against the
+    oracle, with both row passes with combine: the last FFT stage across the
+    workgroup's rows (xrow, the default where it exists) and the separate
+    combine exchange (classic)."""
+    say("case split batch %d shape %dx%d m1 %d %s" % ((batch,) + shape + (m1, combine)))
     monkeypatch.setenv("FFT2D_SPLIT", str(m1))
+    monkeypatch.setenv("FFT2D_COMBINE", combine)
     plan = F.Plan(batch, *shape)
     try:
-        assert ("split=%d " % m1) in plan.describe(), plan.describe()
+        desc = plan.describe()
+        assert ("split=%d " % m1) in desc, desc
+        if combine == "classic":
+            assert " combine]" in desc, desc
         x = synth.complex_grid(m1 + batch, (batch,) + shape)
         xd = dev(x)
         y = host(plan(xd, F.FORWARD))
@@ -296,6 +305,32 @@ def test_split_column_kernel_width(F, shape, mode, col_e, monkeypatch):
         xd = dev(x)
         check(host(plan(xd, F.FORWARD)), oracle.fft2_forward(x), "split column E=%d %dx%d fwd" % ((col_e,) + shape))
         check(host(plan(xd, F.INVERSE)), oracle.ifft2(x), "split column E=%d %dx%d inv" % ((col_e,) + shape))
+    finally:
+        plan.close()
+
+
+@pytest.mark.parametrize("shape,stages", [((4096, 4096), "two"), ((2, 4096, 4096), "two"), ((8192, 2048), "two"),
+                                          ((8192, 8192), "two"), ((16384, 2048), "two"),
+                                          ((16384, 2048), "classic"), ((8192, 8192), "classic")],
+                         ids=lambda v: str(v))
+def test_split_column_stages(F, shape, stages, monkeypatch):
+    """Split plans whose column pass runs a two-stage radix schedule (32 x 32
+    for 1024-point columns, 64 x 32 for 2048-point columns: one LDS exchange;
+    the default) and three stages (classic), forward and inverse, against the
+    oracle."""
+    say("case split column stages %s %s" % (shape, stages))
+    monkeypatch.setenv("FFT2D_COLUMN_STAGES", stages)
+    batch, rows, cols = (1,) + shape if len(shape) == 2 else shape
+    plan = F.Plan(batch, rows, cols)
+    try:
+        desc = plan.describe()
+        say(desc)
+        col = desc[desc.index("col["):]
+        assert ("radix=32x32 " in col or "radix=64x32 " in col) == (stages == "two"), desc
+        x = synth.complex_grid(50 + cols // 1024, (batch, rows, cols) if batch > 1 else (rows, cols))
+        xd = dev(x)
+        check(host(plan(xd, F.FORWARD)), oracle.fft2_forward(x), "column stages %s %s fwd" % (stages, shape))
+        check(host(plan(xd, F.INVERSE)), oracle.ifft2(x), "column stages %s %s inv" % (stages, shape))
     finally:
         plan.close()
 
