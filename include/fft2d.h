@@ -100,7 +100,8 @@ typedef struct fft2d_plan_s* fft2d_plan_t;
  * stage of its row FFT across its M1 rows, so that the M1-point combine needs
  * no LDS exchange of its own (FFT2D_COMBINE=xrow | classic), and column
  * passes of 1024 and 2048 points use two radix stages (32 x 32, 64 x 32:
- * FFT2D_COLUMN_STAGES=two | classic). Grids of 32 x 32,
+ * FFT2D_COLUMN_STAGES=two | classic), with nontemporal loads for grids of at
+ * least 256 MiB (FFT2D_COLUMN_NT=auto | on | off). Grids of 32 x 32,
  * 32 x 64, 64 x 32, 64 x 64, 32 x 128, 128 x 32, 64 x 128, 128 x 64, 128 x 128,
  * 32 x 256, 256 x 32, 64 x 256 and 256 x 64 run both passes in one whole-grid
  * launch (one workgroup per grid, every point read and written once) when the

@@ -136,6 +136,19 @@ int use_xcd_remap(const PassKernel& k) {
   return k.C * 8 < 128 ? 1 : 0;
 }
 
+// Whether a split plan's two-stage column pass loads its input nontemporally
+// (the row pass's output, read once): for grids of at least 256 MiB, about
+// the MALL's size, whose intermediate then comes mostly from HBM. Measured on
+// MI355X, column pass, forward, 1 GiB read before each transform: 8192^2
+// 253.0 against 275.9 us, 16384 x 2048 101.3 against 109.1 us, 4096^2 (from
+// the MALL) 45.6 against 45.3 us. FFT2D_COLUMN_NT=auto|on|off overrides.
+bool use_nontemporal_columns(int64_t points) {
+  const char* env = std::getenv("FFT2D_COLUMN_NT");
+  if (env && std::strcmp(env, "on") == 0) return true;
+  if (env && std::strcmp(env, "off") == 0) return false;
+  return points * 8 >= (int64_t(256) << 20);
+}
+
 // Whether a split plan's row pass runs the combine kernel whose last FFT stage
 // works across the workgroup's rows (rowx_kernel: one LDS exchange fewer)
 // rather than the one with a separate combine exchange (rowc_kernel), where
@@ -451,7 +464,8 @@ fft2d_status select_kernels(fft2d_plan_s* p, int64_t batch, int64_t rows, int64_
 
   if (p->m1 > 1) {
     p->row_k = find_combine_kernel((int)cols, (int)p->m1, use_cross_row_combine());
-    p->col_k = find_split_column_kernel((int)p->m2, use_wide_columns(), use_two_stage_columns());
+    p->col_k = find_split_column_kernel((int)p->m2, use_wide_columns(), use_two_stage_columns(),
+                                        use_nontemporal_columns(batch * rows * cols));
     if (!p->col_k) p->col_k = find_pass_kernel((int)p->m2, true);
   } else {
     if (cols > 1) p->row_k = find_pass_kernel((int)cols, false);

@@ -86,10 +86,10 @@ const PassKernel* find_few_tiles_kernel(int L, bool colmode);
 // (rowx_kernel) where both exist.
 const PassKernel* find_combine_kernel(int L, int m1, bool cross_row = true);
 // Column pass for the length-M2 columns of a split transform; `two_stage`
-// prefers a two-stage radix schedule (one LDS exchange) where there is one,
-// then `wide` the 64-points-per-thread variant where there is one (large
-// grids).
-const PassKernel* find_split_column_kernel(int L, bool wide = false, bool two_stage = false);
+// prefers a two-stage radix schedule (one LDS exchange) where there is one
+// (`nt`: its variant with nontemporal input loads), then `wide` the
+// 64-points-per-thread variant where there is one (large grids).
+const PassKernel* find_split_column_kernel(int L, bool wide = false, bool two_stage = false, bool nt = false);
 // Whole-grid kernel for rows x cols grids (nullptr if none).
 const GridKernel* find_grid_kernel(int rows, int cols);
 // All compiled variants for a length (for the autotuner); returns the count.

@@ -46,10 +46,10 @@ const PassKernel* find_combine_kernel(int L, int m1, bool cross_row) {
   return any;
 }
 
-const PassKernel* find_split_column_kernel(int L, bool wide, bool two_stage) {
+const PassKernel* find_split_column_kernel(int L, bool wide, bool two_stage, bool nt) {
   int n = 0;
   if (two_stage) {
-    const PassKernel* tab = split_col_two_stage_kernel_table(&n);
+    const PassKernel* tab = split_col_two_stage_kernel_table(&n, nt);
     for (int i = 0; i < n; ++i)
       if (tab[i].L == L && (wide || tab[i].E <= 32)) return &tab[i];
   }

@@ -66,6 +66,11 @@ using S2048B = Cfg<2048, 64, 16, 2, true, 64, 32>;
 const PassKernel kSplitColTwoStageKernels[] = {
     describe<S1024B, kKindPass, 1, false, true>(), describe<S2048B, kKindPass, 1, false, true>(),
 };
+// The same with nontemporal input loads, for grids larger than the MALL (the
+// column pass then reads the row pass's output from HBM).
+const PassKernel kSplitColTwoStageNtKernels[] = {
+    describe<S1024B, kKindPass, 1, true, true>(), describe<S2048B, kKindPass, 1, true, true>(),
+};
 
 }  // namespace
 
@@ -79,7 +84,11 @@ const PassKernel* split_col_kernel_table(int* count) {
   return kSplitColKernels;
 }
 
-const PassKernel* split_col_two_stage_kernel_table(int* count) {
+const PassKernel* split_col_two_stage_kernel_table(int* count, bool nt) {
+  if (nt) {
+    *count = (int)(sizeof(kSplitColTwoStageNtKernels) / sizeof(kSplitColTwoStageNtKernels[0]));
+    return kSplitColTwoStageNtKernels;
+  }
   *count = (int)(sizeof(kSplitColTwoStageKernels) / sizeof(kSplitColTwoStageKernels[0]));
   return kSplitColTwoStageKernels;
 }

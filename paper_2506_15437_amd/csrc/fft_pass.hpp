@@ -196,12 +196,58 @@ __device__ __forceinline__ float2 rotate(float2 v) {
   }
 }
 
+// Radix-2 butterfly with the twiddle w = W_N^Q (exponent sign DIR):
+// (lo, hi) <- (lo + w hi, lo - w hi). Trivial twiddles (1, -1, +-i) are
+// swaps. For odd multiples of pi/4 (|cos| = |sin| = c) w hi = c (u, v) with
+// u, v one addition each, and each output component is one FMA. A general
+// twiddle gives lo - w hi in two FMAs per component and lo + w hi as
+// 2 lo - (lo - w hi), one FMA per component: six instructions where a complex
+// multiplication and two complex additions take eight.
+template <int DIR, int N, int Q>
+__device__ __forceinline__ void bfly(float2& lo, float2& hi) {
+  constexpr int q = ((Q % N) + N) % N;
+  if constexpr (q == 0 || 2 * q == N || 4 * q == N || 4 * q == 3 * N) {
+    const float2 f = rotate<DIR, N, Q>(hi);
+    hi = csub(lo, f);
+    lo = cadd(lo, f);
+  } else if constexpr ((8 * q) % N == 0) {
+    constexpr CosSin w = unit_root(q, N);
+    constexpr float c = (float)w.c;
+    constexpr float s = (float)(DIR * w.s);
+    static_assert(s == c || s == -c, "an odd multiple of pi/4 has |cos| = |sin|");
+    constexpr float sg = (s == c) ? 1.0f : -1.0f;
+    const float u = hi.x - sg * hi.y;
+    const float v = sg * hi.x + hi.y;
+    hi = make_float2(fmaf(-c, u, lo.x), fmaf(-c, v, lo.y));
+    lo = make_float2(fmaf(c, u, lo.x), fmaf(c, v, lo.y));
+  } else {
+    constexpr CosSin w = unit_root(q, N);
+    constexpr float c = (float)w.c;
+    constexpr float s = (float)(DIR * w.s);
+    const float2 h = make_float2(fmaf(-c, hi.x, fmaf(s, hi.y, lo.x)), fmaf(-c, hi.y, fmaf(-s, hi.x, lo.y)));
+    lo = make_float2(fmaf(2.0f, lo.x, -h.x), fmaf(2.0f, lo.y, -h.y));
+    hi = h;
+  }
+}
+
+// First radix-2 step of an R-point DFT whose inputs a[k] are multiplied by
+// run-time twiddles w[k] first (w[0] = 1): the pair (a[k] w[k], a[k + R/2]
+// w[k + R/2]) gives lo - w' hi in two FMAs per component after the complex
+// product a[k] w[k], and lo + w' hi = 2 lo - (lo - w' hi) in one.
+__device__ __forceinline__ void bfly_tw(float2& lo, float2& hi, float2 wl, float2 wh, bool lo_one) {
+  const float2 l = lo_one ? lo : cmul(lo, wl);
+  const float2 h = make_float2(fmaf(-wh.x, hi.x, fmaf(wh.y, hi.y, l.x)), fmaf(-wh.x, hi.y, fmaf(-wh.y, hi.x, l.y)));
+  lo = make_float2(fmaf(2.0f, l.x, -h.x), fmaf(2.0f, l.y, -h.y));
+  hi = h;
+}
+
 // In-register R-point DFT (exponent sign DIR), natural order in and out,
 // computed as log2 R radix-2 decimation-in-time steps on bit-reversed data:
 // at the step of span h, points lo and lo + h (lo mod h = q) combine with the
-// twiddle W_{2h}^q.
-template <int R, int DIR>
-__device__ __forceinline__ void dft(float2 (&a)[R]) {
+// twiddle W_{2h}^q. With TW, input k is first multiplied by w[k] (k >= 1;
+// w[0] is not read), fused into the first step.
+template <int R, int DIR, bool TW = false>
+__device__ __forceinline__ void dft_impl(float2 (&a)[R], const float2 (&w)[R]) {
   float2 b[R];
   static_for<0, R>([&](auto I) {
     constexpr int i = decltype(I)::value;
@@ -214,9 +260,13 @@ __device__ __forceinline__ void dft(float2 (&a)[R]) {
         constexpr int q = decltype(Qv)::value;
         constexpr int lo = decltype(G)::value * 2 * h + q;
         constexpr int hi = lo + h;
-        const float2 f = rotate<DIR, 2 * h, q>(b[hi]);
-        b[hi] = csub(b[lo], f);
-        b[lo] = cadd(b[lo], f);
+        if constexpr (TW && h == 1) {
+          // b[lo] = a[k], b[hi] = a[k + R/2] with k = bitrev(lo)
+          constexpr int k = bitrev<R>(lo);
+          bfly_tw(b[lo], b[hi], w[k], w[k + R / 2], k == 0);
+        } else {
+          bfly<DIR, 2 * h, q>(b[lo], b[hi]);
+        }
       });
     });
   });
@@ -224,6 +274,18 @@ __device__ __forceinline__ void dft(float2 (&a)[R]) {
     constexpr int i = decltype(I)::value;
     a[i] = b[i];
   });
+}
+
+template <int R, int DIR>
+__device__ __forceinline__ void dft(float2 (&a)[R]) {
+  const float2 none[R] = {};
+  dft_impl<R, DIR, false>(a, none);
+}
+
+// R-point DFT of a[k] * w[k] (w[0] = 1 is not read).
+template <int R, int DIR>
+__device__ __forceinline__ void dft_tw(float2 (&a)[R], const float2 (&w)[R]) {
+  dft_impl<R, DIR, true>(a, w);
 }
 
 // ------------------------------------------------------------ configuration
@@ -349,14 +411,17 @@ __device__ __forceinline__ void run_pass(float2 (&d)[K::E], float2* lds, int tt,
     });
     if constexpr (p > 0 && ARITH) {
       const uint32_t voff = (uint32_t)(b & (Ns - 1)) * 8u;
+      float2 w[R];
+      w[0] = make_float2(1.0f, 0.0f);
       static_for<1, R>([&](auto Rr) {
         constexpr int r = decltype(Rr)::value;
-        float2 w = tw.load(voff, (uint32_t)(K::tw_off(p) + (r - 1) * Ns) * 8u);
-        if constexpr (DIR > 0) w.y = -w.y;
-        x[r] = cmul(x[r], w);
+        w[r] = tw.load(voff, (uint32_t)(K::tw_off(p) + (r - 1) * Ns) * 8u);
+        if constexpr (DIR > 0) w[r].y = -w[r].y;
       });
+      dft_tw<R, DIR>(x, w);
+    } else if constexpr (ARITH) {
+      dft<R, DIR>(x);
     }
-    if constexpr (ARITH) dft<R, DIR>(x);
     static_for<0, R>([&](auto S) {
       constexpr int s = decltype(S)::value;
       if constexpr (last) d[i + NB * s] = x[s];
@@ -650,6 +715,7 @@ __device__ __forceinline__ void rowx_tile(const PassArgs& a, int64_t w, float2* 
   float2 wk[M1];
   if constexpr (MODE == 0) {
     float2 wl[RL];
+    wl[0] = make_float2(1.0f, 0.0f);
     static_for<1, RL>([&](auto Rr) {
       constexpr int r = decltype(Rr)::value;
       float2 v = tw.load((uint32_t)t * 8u, (uint32_t)(K::tw_off(K::P - 1) + (r - 1) * SPAN) * 8u);
@@ -665,11 +731,8 @@ __device__ __forceinline__ void rowx_tile(const PassArgs& a, int64_t w, float2* 
     static_for<0, M1>([&](auto Cc) {
       constexpr int cr = decltype(Cc)::value;
       float2 x[RL];
-      static_for<0, RL>([&](auto Rr) {
-        constexpr int r = decltype(Rr)::value;
-        x[r] = (r == 0) ? d[cr * RL] : cmul(d[cr * RL + r], wl[r]);
-      });
-      dft<RL, DIR>(x);
+      static_for<0, RL>([&](auto Rr) { x[decltype(Rr)::value] = d[cr * RL + decltype(Rr)::value]; });
+      dft_tw<RL, DIR>(x, wl);
       static_for<0, RL>([&](auto S) { d[cr * RL + decltype(S)::value] = x[decltype(S)::value]; });
     });
   }

@@ -12,7 +12,7 @@ const PassKernel* col_few_kernel_table(int* count);
 const PassKernel* combine_kernel_table(int* count);
 const PassKernel* split_col_kernel_table(int* count);
 const PassKernel* split_col_wide_kernel_table(int* count);
-const PassKernel* split_col_two_stage_kernel_table(int* count);
+const PassKernel* split_col_two_stage_kernel_table(int* count, bool nt);
 const GridKernel* grid_kernel_table(int* count);
 
 }  // namespace fft2d

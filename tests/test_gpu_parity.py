@@ -311,22 +311,27 @@ def test_split_column_kernel_width(F, shape, mode, col_e, monkeypatch):
 
 @pytest.mark.parametrize("shape,stages", [((4096, 4096), "two"), ((2, 4096, 4096), "two"), ((8192, 2048), "two"),
                                           ((8192, 8192), "two"), ((16384, 2048), "two"),
-                                          ((16384, 2048), "classic"), ((8192, 8192), "classic")],
+                                          ((16384, 2048), "classic"), ((8192, 8192), "classic"),
+                                          ((4096, 4096), "two-nt"), ((8192, 8192), "two-plain")],
                          ids=lambda v: str(v))
 def test_split_column_stages(F, shape, stages, monkeypatch):
     """Split plans whose column pass runs a two-stage radix schedule (32 x 32
     for 1024-point columns, 64 x 32 for 2048-point columns: one LDS exchange;
-    the default) and three stages (classic), forward and inverse, against the
-    oracle."""
+    the default; with nontemporal loads forced on or off) and three stages
+    (classic), forward and inverse, against the oracle."""
     say("case split column stages %s %s" % (shape, stages))
-    monkeypatch.setenv("FFT2D_COLUMN_STAGES", stages)
+    monkeypatch.setenv("FFT2D_COLUMN_STAGES", stages.split("-")[0])
+    if "-" in stages:  # nontemporal column loads forced on (two-nt) or off (two-plain)
+        monkeypatch.setenv("FFT2D_COLUMN_NT", "on" if stages.endswith("nt") else "off")
     batch, rows, cols = (1,) + shape if len(shape) == 2 else shape
     plan = F.Plan(batch, rows, cols)
     try:
         desc = plan.describe()
         say(desc)
         col = desc[desc.index("col["):]
-        assert ("radix=32x32 " in col or "radix=64x32 " in col) == (stages == "two"), desc
+        assert ("radix=32x32 " in col or "radix=64x32 " in col) == stages.startswith("two"), desc
+        if "-" in stages:
+            assert (" nt" in col) == stages.endswith("nt"), desc
         x = synth.complex_grid(50 + cols // 1024, (batch, rows, cols) if batch > 1 else (rows, cols))
         xd = dev(x)
         check(host(plan(xd, F.FORWARD)), oracle.fft2_forward(x), "column stages %s %s fwd" % (stages, shape))
