@@ -109,7 +109,9 @@ typedef struct fft2d_plan_s* fft2d_plan_t;
  * points, at least 32 grids of 8192 points, 128 grids of 16384); FFT2D_GRID
  * (off | auto | on) overrides that choice. Plain passes that would run about
  * one tile per CU or fewer use narrower tiles (FFT2D_FEW_TILES
- * off | auto | on). Batches of more than 2^31 points run
+ * off | auto | on); for 1024-point rows that is one row per wave, whose
+ * second exchange runs in registers across the wave's lanes
+ * (FFT2D_ROW_SHUFFLE on | off). Batches of more than 2^31 points run
  * as several launches of whole grids (a HIP launch holds fewer than 2^32
  * work-items); if one of those launches fails, the earlier ones stay enqueued.
  * Must be called with a GPU present.

@@ -136,6 +136,17 @@ int use_xcd_remap(const PassKernel& k) {
   return k.C * 8 < 128 ? 1 : 0;
 }
 
+// Whether the few-tiles row pass of 1024-point rows (one row per wave) runs
+// its second exchange in registers across the wave's 16-lane rows
+// (v_permlane32_swap / v_permlane16_swap) rather than through the LDS.
+// Measured on MI355X, row pass of 1024 x 1024, forward, 1 GiB read before
+// each transform: 6.95 against 7.06 us (means of four runs each); 512 x 1024
+// 5.73 against 5.89 us. FFT2D_ROW_SHUFFLE=on|off overrides (default on).
+bool use_wave_shuffle() {
+  const char* env = std::getenv("FFT2D_ROW_SHUFFLE");
+  return !(env && std::strcmp(env, "off") == 0);
+}
+
 // Whether a split plan's two-stage column pass loads its input nontemporally
 // (the row pass's output, read once): for grids of at least 256 MiB, about
 // the MALL's size, whose intermediate then comes mostly from HBM. Measured on
@@ -471,7 +482,7 @@ fft2d_status select_kernels(fft2d_plan_s* p, int64_t batch, int64_t rows, int64_
     if (cols > 1) p->row_k = find_pass_kernel((int)cols, false);
     if (rows > 1) p->col_k = find_pass_kernel((int)rows, true);
     if (p->row_k && use_few_tiles_kernel(batch * rows, p->row_k->C, false)) {
-      if (const PassKernel* f = find_few_tiles_kernel((int)cols, false)) p->row_k = f;
+      if (const PassKernel* f = find_few_tiles_kernel((int)cols, false, use_wave_shuffle())) p->row_k = f;
     }
     if (p->col_k && use_few_tiles_kernel(batch * cols, p->col_k->C, true)) {
       if (const PassKernel* f = find_few_tiles_kernel((int)rows, true)) p->col_k = f;
@@ -783,7 +794,8 @@ fft2d_status fft2d_plan_describe(fft2d_plan_t plan, char* buf, int64_t buflen) {
     for (int i = 0; i < k->npass; ++i) s += (i ? "x" : "") + std::to_string(k->radix[i]);
     s += " E=" + std::to_string(k->E) + " C=" + std::to_string(k->C) + " Q=" + std::to_string(k->Q) +
          " threads=" + std::to_string(k->threads) + " lds=" + std::to_string(k->lds_bytes) +
-         (k->wpe > 1 ? " wpe=" + std::to_string(k->wpe) : "") + (k->nt ? " nt" : "");
+         (k->wpe > 1 ? " wpe=" + std::to_string(k->wpe) : "") + (k->nt ? " nt" : "") +
+         (k->shuffle ? " shuffle" : "");
     return s;
   };
   if (plan->kind == kUniform) {

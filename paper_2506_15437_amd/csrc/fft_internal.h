@@ -54,6 +54,7 @@ struct PassKernel {
   int colmode;
   int combine;  // row pass with an M1 = C point combine across its rows (split column transform)
   int xrow;     // combine kernel whose last FFT stage runs across its rows (one LDS exchange fewer)
+  int shuffle;  // an exchange runs in registers across the wave's lanes instead of through the LDS
   int wpe;  // minimum waves per SIMD the kernel was compiled for
   int nt;   // nontemporal input loads
   int npass;
@@ -79,8 +80,9 @@ struct GridKernel {
 // Default kernel for a length L in [2, 16384] (power of two); nullptr otherwise.
 const PassKernel* find_pass_kernel(int L, bool colmode);
 // Pass of length L with narrower tiles, for passes with few tiles (nullptr
-// if none).
-const PassKernel* find_few_tiles_kernel(int L, bool colmode);
+// if none); `shuffle` prefers a variant with an exchange in registers across
+// the wave's lanes where there is one.
+const PassKernel* find_few_tiles_kernel(int L, bool colmode, bool shuffle = false);
 // Row pass with an M1-point combine across M1 rows of length L (nullptr if
 // none); `cross_row` prefers the variant whose last stage runs across the rows
 // (rowx_kernel) where both exist.

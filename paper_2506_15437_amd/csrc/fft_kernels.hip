@@ -26,12 +26,16 @@ const PassKernel* find_pass_kernel(int L, bool colmode) {
   return nullptr;
 }
 
-const PassKernel* find_few_tiles_kernel(int L, bool colmode) {
+const PassKernel* find_few_tiles_kernel(int L, bool colmode, bool shuffle) {
   int n = 0;
   const PassKernel* tab = colmode ? col_few_kernel_table(&n) : row_few_kernel_table(&n);
-  for (int i = 0; i < n; ++i)
-    if (tab[i].L == L) return &tab[i];
-  return nullptr;
+  const PassKernel* any = nullptr;
+  for (int i = 0; i < n; ++i) {
+    if (tab[i].L != L) continue;
+    if ((tab[i].shuffle != 0) == shuffle) return &tab[i];
+    if (!any) any = &tab[i];
+  }
+  return any;
 }
 
 const PassKernel* find_combine_kernel(int L, int m1, bool cross_row) {

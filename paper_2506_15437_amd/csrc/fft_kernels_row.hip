@@ -30,6 +30,7 @@ using R16384 = Cfg<16384, 64, 1, 2, false, 16, 16, 16, 4>;  // 256 threads, two 
 using R1024F = Cfg<1024, 16, 1, 1, false, 16, 16, 4>;
 const PassKernel kRowFewKernels[] = {
     describe<R1024F, kKindPass, 1, true, true>(),
+    describe<R1024F, kKindWaveRow, 1, true, true>(),  // second exchange in registers (v_permlane16/32_swap)
 };
 
 const PassKernel kRowKernels[] = {

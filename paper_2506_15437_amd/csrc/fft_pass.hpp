@@ -374,6 +374,7 @@ struct Cfg {
 constexpr int kKindPass = 0;
 constexpr int kKindCombine = 1;
 constexpr int kKindCrossRow = 2;
+constexpr int kKindWaveRow = 3;
 
 __device__ __forceinline__ int xcd_remap(int b, int nb) {
   // Consecutive workgroup ids are dispatched round-robin over the 8 XCDs; give
@@ -393,7 +394,8 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
 // tt + T j of its own vector (the next pass's inputs); 1 (row mode, last
 // exchange of a row pass with cross-row last stage, see rowx_tile), for every
 // row c' of the workgroup the points t + r L/RL (r < RL, RL = the last radix)
-// into d[c' RL + r], t the thread's index in the workgroup.
+// into d[c' RL + r], t the thread's index in the workgroup; 2, no exchange:
+// output s of butterfly i stays in d[i R + s].
 template <class K, int DIR, int p, int SB = 0, bool ARITH = true, int RD = 0>
 __device__ __forceinline__ void run_pass(float2 (&d)[K::E], float2* lds, int tt, int c, const Buf& tw) {
   constexpr int R = K::radix(p);
@@ -431,7 +433,10 @@ __device__ __forceinline__ void run_pass(float2 (&d)[K::E], float2* lds, int tt,
     // above this one (bounds register pressure at some latency cost).
     if constexpr (SB != 0) __builtin_amdgcn_sched_barrier(0);
   });
-  if constexpr (!last) {
+  if constexpr (!last && RD == 2) {
+    // no exchange: output s of butterfly i stays in d[i R + s] (the caller moves it)
+    static_for<0, K::E>([&](auto J) { d[decltype(J)::value] = o[decltype(J)::value]; });
+  } else if constexpr (!last) {
     constexpr int EQ = K::E / K::Q;
     // writes of butterfly i (positions relative to round h's first point)
     auto put = [&](auto I, int h) {
@@ -488,6 +493,87 @@ __device__ __forceinline__ void run_pass(float2 (&d)[K::E], float2* lds, int tt,
       __syncthreads();
     });
   }
+}
+
+// Exchange of 4 x 4 blocks across a wave's four 16-lane rows in registers:
+// for every B < 4 the registers v[4B + c] (c < 4) become w[A] with w[A] on
+// row c equal to v[4B + c] on row A, stored to v[4A + B] (lanes within a row
+// keep their data). Two v_permlane32_swap (rows 2, 3 of one register against
+// rows 0, 1 of another) and two v_permlane16_swap (odd rows against even
+// rows) per block and component.
+__device__ __forceinline__ void swap32(float& a, float& b) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(unsigned, a), __builtin_bit_cast(unsigned, b),
+                                                  false, false);
+  a = __builtin_bit_cast(float, (unsigned)r[0]);
+  b = __builtin_bit_cast(float, (unsigned)r[1]);
+}
+__device__ __forceinline__ void swap16(float& a, float& b) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__builtin_bit_cast(unsigned, a), __builtin_bit_cast(unsigned, b),
+                                                  false, false);
+  a = __builtin_bit_cast(float, (unsigned)r[0]);
+  b = __builtin_bit_cast(float, (unsigned)r[1]);
+}
+__device__ __forceinline__ void transpose_rows4x4(float2 (&v)[16]) {
+  float2 w[16];
+  static_for<0, 4>([&](auto Bb) {
+    constexpr int B = decltype(Bb)::value;
+    float2 x0 = v[4 * B], x1 = v[4 * B + 1], x2 = v[4 * B + 2], x3 = v[4 * B + 3];
+    swap32(x0.x, x2.x);
+    swap32(x0.y, x2.y);
+    swap32(x1.x, x3.x);
+    swap32(x1.y, x3.y);
+    swap16(x0.x, x1.x);
+    swap16(x0.y, x1.y);
+    swap16(x2.x, x3.x);
+    swap16(x2.y, x3.y);
+    w[B] = x0;
+    w[4 + B] = x1;
+    w[8 + B] = x2;
+    w[12 + B] = x3;
+  });
+  static_for<0, 16>([&](auto I) { v[decltype(I)::value] = w[decltype(I)::value]; });
+}
+
+// One 1024-point row per 64-lane wave (radix 16, 16, 4; 16 points per lane):
+// the exchange after the first pass goes through the LDS, the one after the
+// second runs in registers. Pass 1 sends output s = 4B + c of lane 16A + l to
+// point 256 A + l + 64 B + 16 c, which the last pass reads as register 4A + B
+// of lane 16c + l: a 4 x 4 transpose of (16-lane row, register) blocks.
+template <class K, int DIR, int AUX, int MODE = 0>
+__device__ __forceinline__ void row_wave_tile(const PassArgs& a, int w, float2* lds) {
+  static_assert(K::L == 1024 && K::T == 64 && K::C == 1 && K::E == 16 && K::P == 3 && K::Q == 1 &&
+                    K::radix(0) == 16 && K::radix(1) == 16 && K::radix(2) == 4 && !K::COL,
+                "one 1024-point row per wave, radix 16 x 16 x 4");
+  const int tt = threadIdx.x;
+  const int64_t base = (int64_t)w * K::L;
+  const Buf src(a.in + base, span_bytes(a.total, base));
+  const Buf dst(a.out + base, span_bytes(a.total, base));
+  const Buf tw(a.tw, (uint32_t)a.tw_count * 8u);
+  float2 d[K::E];
+  static_for<0, K::E>([&](auto J) {
+    d[decltype(J)::value] = src.load<AUX>((uint32_t)tt * 8u, (uint32_t)(K::T * decltype(J)::value) * 8u);
+  });
+  if constexpr (MODE < 2) {
+    run_pass<K, DIR, 0, 0, MODE == 0>(d, lds, tt, 0, tw);
+    run_pass<K, DIR, 1, 0, MODE == 0, 2>(d, lds, tt, 0, tw);
+    transpose_rows4x4(d);
+    run_pass<K, DIR, 2, 0, MODE == 0>(d, lds, tt, 0, tw);
+  }
+  if (w < a.nvec) {
+    const float sc = a.scale;
+    static_for<0, K::E>([&](auto J) {
+      constexpr int j = decltype(J)::value;
+      dst.store(make_float2(d[j].x * sc, d[j].y * sc), (uint32_t)tt * 8u, (uint32_t)(K::T * j) * 8u);
+    });
+  }
+}
+
+// MODE as for fft_tile (1: loads, exchanges and stores only; 2: loads and
+// stores only).
+template <class K, int DIR, bool NT, int MODE = 0>
+__global__ __launch_bounds__(64) void row_wave_kernel(PassArgs a) {
+  __shared__ float2 lds[K::LDS_ELEMS];
+  row_wave_tile<K, DIR, NT ? kAuxNontemporal : 0, MODE>(a, blockIdx.x, lds);
 }
 
 // Conjugation and scaling of one tile's input and output. A forward-sign
@@ -880,6 +966,15 @@ hipError_t launch_rowx(const PassArgs& a, int dir, hipStream_t s, hipEvent_t t0,
   return hipGetLastError();
 }
 
+template <class K, int WPE, bool NT>
+hipError_t launch_wave(const PassArgs& a, int dir, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
+  if (t0 != nullptr || t1 != nullptr)
+    return launch_timed(dir < 0 ? row_wave_kernel<K, -1, NT> : row_wave_kernel<K, +1, NT>, a, K::THREADS, s, t0, t1);
+  if (dir < 0) hipLaunchKernelGGL((row_wave_kernel<K, -1, NT>), dim3(a.nblocks), dim3(K::THREADS), 0, s, a);
+  else hipLaunchKernelGGL((row_wave_kernel<K, +1, NT>), dim3(a.nblocks), dim3(K::THREADS), 0, s, a);
+  return hipGetLastError();
+}
+
 // Measurement variants (MODE 1: data movement without arithmetic, MODE 2:
 // loads and stores only) of a pass, launched like launch_pass/launch_rowc
 // with the forward sign (events optional).
@@ -890,6 +985,8 @@ hipError_t launch_probe(const PassArgs& a, int mode, hipStream_t s, hipEvent_t t
     k = mode == 1 ? rowc_kernel<K, -1, WPE, 0, NT, 1> : rowc_kernel<K, -1, WPE, 0, NT, 2>;
   else if constexpr (KIND == kKindCrossRow)
     k = mode == 1 ? rowx_kernel<K, -1, WPE, 0, NT, 1> : rowx_kernel<K, -1, WPE, 0, NT, 2>;
+  else if constexpr (KIND == kKindWaveRow)
+    k = mode == 1 ? row_wave_kernel<K, -1, NT, 1> : row_wave_kernel<K, -1, NT, 2>;
   else k = mode == 1 ? pass_kernel<K, -1, NT, WPE, 0, 1> : pass_kernel<K, -1, NT, WPE, 0, 2>;
   if (t0 != nullptr || t1 != nullptr) return launch_timed(k, a, K::THREADS, s, t0, t1);
   hipLaunchKernelGGL(k, dim3(a.nblocks), dim3(K::THREADS), 0, s, a);
@@ -916,7 +1013,8 @@ constexpr PassKernel meta() {
 
 // KIND: kKindPass (a plain row or column pass), kKindCombine (row pass with
 // an M1 = C point combine, rowc_kernel) or kKindCrossRow (the same with the
-// last stage across rows, rowx_kernel).
+// last stage across rows, rowx_kernel) or kKindWaveRow (one 1024-point row
+// per wave with its second exchange in registers, row_wave_kernel).
 // WPE: minimum waves per SIMD the compiler must allow (bounds VGPR use).
 // NT: nontemporal loads of the input (row passes read data not reused soon;
 // measured faster from HBM, slower when the data already sits in the MALL).
@@ -924,8 +1022,9 @@ constexpr PassKernel meta() {
 template <class K, int KIND = kKindPass, int WPE = 1, bool NT = !K::COL, bool PROBE = false>
 constexpr PassKernel describe() {
   PassKernel k{};
-  k.combine = KIND != kKindPass ? K::C : 0;
+  k.combine = (KIND == kKindCombine || KIND == kKindCrossRow) ? K::C : 0;
   k.xrow = KIND == kKindCrossRow ? 1 : 0;
+  k.shuffle = KIND == kKindWaveRow ? 1 : 0;
   k.L = K::L;
   k.E = K::E;
   k.T = K::T;
@@ -940,6 +1039,7 @@ constexpr PassKernel describe() {
   k.nt = NT ? 1 : 0;
   if constexpr (KIND == kKindCombine) k.launch = &launch_rowc<K, WPE, NT>;
   else if constexpr (KIND == kKindCrossRow) k.launch = &launch_rowx<K, WPE, NT>;
+  else if constexpr (KIND == kKindWaveRow) k.launch = &launch_wave<K, WPE, NT>;
   else k.launch = &launch_pass<K, WPE, NT>;
   if constexpr (PROBE) k.launch_probe = &launch_probe<K, WPE, NT, KIND>;
   return k;

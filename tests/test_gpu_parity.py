@@ -340,6 +340,31 @@ def test_split_column_stages(F, shape, stages, monkeypatch):
         plan.close()
 
 
+@pytest.mark.parametrize("mode", ["on", "off"])
+@pytest.mark.parametrize("shape", [(1024, 1024), (512, 1024), (3, 1, 1024), (4096, 1024)], ids=lambda v: str(v))
+def test_row_wave_shuffle(F, shape, mode, monkeypatch):
+    """The 1024-point row pass with one row per wave, its second exchange in
+    registers across the wave's 16-lane rows (v_permlane32_swap and
+    v_permlane16_swap; on, the default) or through the LDS (off), forward and
+    inverse, against the oracle."""
+    say("case row wave shuffle %s %s" % (shape, mode))
+    monkeypatch.setenv("FFT2D_ROW_SHUFFLE", mode)
+    monkeypatch.setenv("FFT2D_FEW_TILES", "on")
+    monkeypatch.setenv("FFT2D_SPLIT", "off")
+    batch, rows, cols = (1,) + shape if len(shape) == 2 else shape
+    plan = F.Plan(batch, rows, cols)
+    try:
+        desc = plan.describe()
+        say(desc)
+        assert (" shuffle" in desc[desc.index("row["):desc.index("col[")]) == (mode == "on"), desc
+        x = synth.complex_grid(60 + rows // 256, (batch, rows, cols) if batch > 1 else (rows, cols))
+        xd = dev(x)
+        check(host(plan(xd, F.FORWARD)), oracle.fft2_forward(x), "row shuffle %s fwd" % (shape,))
+        check(host(plan(xd, F.INVERSE)), oracle.ifft2(x), "row shuffle %s inv" % (shape,))
+    finally:
+        plan.close()
+
+
 @pytest.mark.parametrize("shape", [(1024, 1024), (512, 512), (2048, 1024)], ids=lambda s: "%dx%d" % s)
 @pytest.mark.parametrize("mode", ["auto", "off"])
 def test_few_tiles_column_kernel(F, shape, mode, monkeypatch):
