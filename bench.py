@@ -69,20 +69,21 @@ def _counter_rows(run_dir):
 
 def kernel_role(name):
     """(kind, direction) of a library pass kernel from its demangled name:
-    kind "row" (pass_kernel in row mode, or rowc_kernel) or "col" (pass_kernel
-    in column mode), direction -1 or +1 (the template argument after the
-    configuration); None for any other kernel. A measurement variant (last
-    template argument 1 or 2) has kind "row-probe" / "col-probe"."""
+    kind "row" (pass_kernel in row mode, rowc_kernel, rowx_kernel or
+    row_wave_kernel) or "col" (pass_kernel in column mode), direction -1 or +1
+    (the template argument after the configuration); None for any other
+    kernel. A measurement variant (MODE template argument 1 or 2) has kind
+    "row-probe" / "col-probe"."""
     import re
-    m = re.search(r"fft2d::dev::(pass_kernel|rowc_kernel)<fft2d::dev::Cfg<([^>]*)>,\s*(-?\d+)([^>]*)>", name)
+    m = re.search(r"fft2d::dev::(pass_kernel|rowc_kernel|rowx_kernel|row_wave_kernel)<fft2d::dev::Cfg<([^>]*)>,"
+                  r"\s*(-?\d+)([^>]*)>", name)
     if not m:
         return None
     kernel, cfg, sign, rest = m.group(1), [v.strip() for v in m.group(2).split(",")], int(m.group(3)), m.group(4)
     kind = "col" if (kernel == "pass_kernel" and cfg[4] == "true") else "row"
     tail = [v.strip() for v in rest.split(",") if v.strip()]
-    if kernel == "pass_kernel" and len(tail) >= 4 and tail[3] in ("1", "2"):
-        kind += "-probe"
-    if kernel == "rowc_kernel" and len(tail) >= 4 and tail[3] in ("1", "2"):
+    mode_at = 1 if kernel == "row_wave_kernel" else 3  # position of MODE after the sign
+    if len(tail) > mode_at and tail[mode_at] in ("1", "2"):
         kind += "-probe"
     return kind, (-1 if sign < 0 else 1)
 

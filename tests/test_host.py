@@ -199,6 +199,12 @@ def test_counter_summaries_reject_a_shifted_trace(tmp_path):
     assert bench.kernel_role(probe) == ("row-probe", -1)
     _write_counters(tmp_path / "extra", rows + [[99, probe, "SQ_WAVES", 1.0], [98, "copyBuffer", "SQ_WAVES", 1.0]])
     assert bench.summarize_counters(str(tmp_path / "extra")) == bench.summarize_counters(str(tmp_path / "ok"))
+    # the other row-pass kernels: last stage across rows, one row per wave
+    rx = "void fft2d::dev::rowx_kernel<fft2d::dev::Cfg<4096, 32, 4, 2, false, 16, 32, 8>, %d, 4, 0, true, %d>(fft2d::PassArgs)"
+    rw = "void fft2d::dev::row_wave_kernel<fft2d::dev::Cfg<1024, 16, 1, 1, false, 16, 16, 4>, %d, true, %d>(fft2d::PassArgs)"
+    assert bench.kernel_role(rx % (-1, 0)) == ("row", -1) and bench.kernel_role(rx % (1, 0)) == ("row", 1)
+    assert bench.kernel_role(rx % (-1, 1)) == ("row-probe", -1)
+    assert bench.kernel_role(rw % (1, 0)) == ("row", 1) and bench.kernel_role(rw % (-1, 2)) == ("row-probe", -1)
     fwd = [[i, n, "SQ_WAVES", 1.0] for i, n in enumerate(ROUND_TRIP_NAMES[:2] * 3)]
     _write_counters(tmp_path / "fwd", fwd)
     assert "pass fwd_col" in bench.summarize_counters(str(tmp_path / "fwd"), roles=bench.FORWARD_ROLES)
