@@ -23,7 +23,7 @@ using R1024 = Cfg<1024, 32, 4, 1, false, 32, 32>;
 using R2048 = Cfg<2048, 16, 2, 1, false, 16, 16, 8>;
 using R4096 = Cfg<4096, 16, 1, 1, false, 16, 16, 16>;
 using R8192 = Cfg<8192, 32, 1, 1, false, 32, 16, 16>;
-using R16384 = Cfg<16384, 64, 1, 2, false, 16, 16, 16, 4>;  // 256 threads, two workgroups per CU
+using R16384 = Cfg<16384, 64, 1, 2, false, 64, 16, 16>;  // 256 threads, two workgroups per CU
 
 // One row of 1024 per 64-thread workgroup, for row passes with few tiles
 // (e.g. one 1024 x 1024 grid: 256 tiles of 4 rows, or 1024 of one).

@@ -32,9 +32,9 @@ using S4096 = Cfg<4096, 32, 8, 2, true, 16, 16, 16>;
 // registers on that stage's outputs, so there is no separate combine exchange.
 using RX8192x4 = Cfg<8192, 32, 4, 2, false, 32, 32, 8>;
 using RX16384x2 = Cfg<16384, 32, 2, 2, false, 32, 32, 16>;
-using RX4096x4 = Cfg<4096, 32, 4, 2, false, 16, 32, 8>;
-using RX2048x8 = Cfg<2048, 32, 8, 2, false, 16, 32, 4>;
-using RX1024x16 = Cfg<1024, 32, 16, 2, false, 16, 32, 2>;
+using RX4096x4 = Cfg<4096, 32, 4, 2, false, 32, 16, 8>;
+using RX2048x8 = Cfg<2048, 32, 8, 2, false, 32, 16, 4>;
+using RX1024x16 = Cfg<1024, 32, 16, 2, false, 32, 16, 2>;
 
 const PassKernel kCombineKernels[] = {
     describe<RC8192x2, kKindCombine, 4>(), describe<RC8192x4, kKindCombine, 1, true, true>(),
