@@ -518,6 +518,60 @@ def device_copy_gbps(torch, iters=20):
     return out
 
 
+def probe_rates(F, torch, iters=10):
+    """The probes behind the pass kernels' design: copies of an 8192 x 8192
+    grid in column tiles of the 8192^2 split column pass's rows (M1 = 4) with
+    128-, 256- and 512-byte row segments (fft2d_probe_tile_copy; every tile
+    256 KiB; only the 128-byte form fits a 2048-point column FFT in one
+    workgroup), plain and nontemporal loads, each copy after a 1 GiB read
+    (mean, GB/s of read + write); and the LDS read and write bandwidth of one
+    1024-thread workgroup per CU with 4-, 8- and 16-byte accesses
+    (fft2d_probe_lds; bytes per clock per CU at the 2.4 GHz peak clock)."""
+    stream = torch.cuda.current_stream()
+    sh = int(stream.cuda_stream)
+    n = 8192
+    x = torch.zeros((n, n), dtype=torch.complex64, device="cuda")
+    y = torch.empty_like(x)
+    scratch = torch.empty(SCRATCH_FLOATS, dtype=torch.float32, device="cuda")
+    out = {}
+
+    def timed(fn, cold):
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(iters + 1)]
+        for a, b in ev:  # torch computes elapsed times only of events it has recorded once
+            a.record(stream)
+            b.record(stream)
+        torch.cuda.synchronize()
+        for a, b in ev:
+            if cold:
+                scratch.sum()
+            fn(a.cuda_event, b.cuda_event)
+        torch.cuda.synchronize()
+        return float(np.mean([a.elapsed_time(b) for a, b in ev[1:]]))
+
+    for cw in (16, 32, 64):
+        for nt in (False, True):
+            ms = timed(lambda a, b: F.fft2d_probe_tile_copy(x.data_ptr(), y.data_ptr(), n, n, cw, 4, nt, a, b, sh),
+                       True)
+            nbytes = 2 * n * n * 8
+            out["tile_copy_%dB%s" % (cw * 8, "_nt" if nt else "")] = {
+                "ms": round(ms, 5), "gbps": round(nbytes / (ms * 1e-3) / 1e9, 1), "frac": _frac(nbytes, ms)}
+    del x, y, scratch
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    sink = torch.empty(cus * 1024, dtype=torch.float32, device="cuda")
+    for width in (4, 8, 16):
+        for write in (False, True):
+            moved = {}
+
+            def run(a, b):
+                moved["bytes"] = F.fft2d_probe_lds(width, write, sink.data_ptr(), sink.numel(), a, b, sh)
+            ms = timed(run, False)
+            out["lds_%s_b%d" % ("write" if write else "read", width * 8)] = {
+                "ms": round(ms, 5), "bytes_per_clk_per_cu": round(moved["bytes"] / (ms * 1e-3) / 2.4e9 / cus, 1)}
+    del sink
+    torch.cuda.empty_cache()
+    return out
+
+
 def vendor_fft_context(F, torch, iters=20):
     """Context only: torch.fft.fft2 (the ROCm vendor FFT that torch calls) and
     fft2d_exec on the same inputs, forward, warm medians of `iters` transforms
@@ -958,6 +1012,8 @@ def main():
             result["roofline"]["frac_of_same_pattern_copy"] = round(passes["row"]["copy_ms"] / passes["row"]["fft_ms"], 4)
         log("bench: device copy bandwidth, 512 MiB to 512 MiB")
         result["device_copy"] = device_copy_gbps(torch)
+        log("bench: column-tile copy and LDS bandwidth probes")
+        result["probes"] = probe_rates(F, torch)
         log("bench: energy per transform (1024 x 1024 and 4096 x 4096)")
         result["energy"] = [energy(F, torch, 1024, 1024, 1.5), energy(F, torch, 4096, 4096, 1.5)]
         log("bench: batched 512 shapes vs 512 plain launches")

@@ -277,6 +277,44 @@ fft2d_status fft2d_exec_pass_ablated(fft2d_plan_t plan, const void* in, void* ou
 fft2d_status fft2d_probe_dft16(int method, const void* in, void* out, int64_t count, int reps, void* start_event,
                                void* stop_event, void* stream);
 
+/*
+ * fft2d_probe_tile_copy -- a measurement aid for the column pass's access
+ * pattern (the paper's 2D FFT reads its columns after a global transpose,
+ * Section 5, Fig. 6): copies a rows x cols complex64 grid from `in` to `out`
+ * in column tiles of `tile_cols` columns (row segments of 8 * tile_cols bytes)
+ * by 512-thread workgroups, lanes over columns first. Tile (k1, hb, cb) holds
+ * rows k1 + residues * (hb * H + m), m < H, H = 2048, 1024, 512 for 16, 32,
+ * 64 columns (so a tile is 256 KiB in every case), the row set of a split
+ * column pass with M1 = residues. out equals in afterwards.
+ *   tile_cols   : 16, 32 or 64 (else FFT2D_ERR_INVALID_SIZE);
+ *   rows, cols  : rows a multiple of residues * H, cols of tile_cols,
+ *                 rows * cols <= 2^28 (else FFT2D_ERR_INVALID_SIZE);
+ *   nontemporal : nonzero loads the input with the nontemporal hint;
+ *   in, out     : device pointers, 8-byte aligned, not overlapping
+ *                 (FFT2D_ERR_MISALIGNED, FFT2D_ERR_OVERLAP);
+ *   start_event, stop_event : both null, or hipEvent_t handles bound to the
+ *                 launch as in fft2d_exec_pass_timed.
+ * Only enqueues work on `stream`.
+ */
+fft2d_status fft2d_probe_tile_copy(const void* in, void* out, int64_t rows, int64_t cols, int tile_cols, int residues,
+                                   int nontemporal, void* start_event, void* stop_event, void* stream);
+
+/*
+ * fft2d_probe_lds -- a measurement aid for the LDS exchanges of the pass
+ * kernels (the on-chip counterpart of the paper's reorderings, Section 4):
+ * one 1024-thread workgroup per compute unit, each thread reading (write = 0)
+ * or writing (write != 0) 4096 times `width_bytes` (4, 8 or 16) at
+ * lane-consecutive addresses of a 128 KiB LDS array. *bytes receives the
+ * bytes moved by the launch (divide by its duration for the bandwidth).
+ *   sink        : device buffer of sink_floats floats, at least 1024 per
+ *                 compute unit (else FFT2D_ERR_INVALID_SIZE), overwritten;
+ *   width_bytes : 4, 8 or 16 (else FFT2D_ERR_INVALID_SIZE);
+ *   start_event, stop_event : as for fft2d_probe_tile_copy.
+ * Enqueues on `stream` after querying the current device.
+ */
+fft2d_status fft2d_probe_lds(int width_bytes, int write, void* sink, int64_t sink_floats, int64_t* bytes,
+                             void* start_event, void* stop_event, void* stream);
+
 /* fft2d_destroy -- free a plan and its device memory. NULL is a no-op. Waits for
  * no stream: the caller must make sure no enqueued work still uses the plan. */
 fft2d_status fft2d_destroy(fft2d_plan_t plan);

@@ -19,8 +19,8 @@ Torch-level API:
 C-ABI-level API (same names as the C functions, pointers as ints):
     fft2d_plan, fft2d_plan_batched, fft2d_exec, fft2d_exec_pass, fft2d_exec_pass_timed,
     fft2d_exec_batched, fft2d_backward, fft2d_destroy, fft2d_plan_describe,
-    fft2d_exec_noalloc (no plan, no allocation), fft2d_exec_pass_ablated and
-    fft2d_probe_dft16 (measurement aids)
+    fft2d_exec_noalloc (no plan, no allocation), fft2d_exec_pass_ablated,
+    fft2d_probe_dft16, fft2d_probe_tile_copy and fft2d_probe_lds (measurement aids)
 """
 
 from __future__ import annotations
@@ -29,6 +29,7 @@ _LIB_NAMES = ("EXPORTS", "FORWARD", "INVERSE", "LIB_PATH", "MAX_LEN", "Fft2dErro
               "fft2d_plan_batched", "fft2d_exec", "fft2d_exec_pass", "fft2d_exec_pass_timed", "fft2d_exec_batched",
               "fft2d_backward", "fft2d_destroy", "fft2d_plan_describe", "fft2d_plan_twiddles", "fft2d_exec_noalloc", "NOALLOC_WORK_BYTES", "fft2d_exec_pass_ablated",
               "ABLATE_ARITHMETIC", "ABLATE_EXCHANGE", "fft2d_probe_dft16", "DFT16_BUTTERFLY", "DFT16_MFMA",
+              "fft2d_probe_tile_copy", "fft2d_probe_lds",
               "status_string",
               "last_error", "version", "pointer_array")
 _API_NAMES = ("Plan", "BatchedPlan", "get_plan", "fft2", "ifft2", "fft2_batched", "FFT2Function", "fft2_diff")

@@ -44,7 +44,8 @@ EXPORTS = ("fft2d_plan", "fft2d_plan_batched", "fft2d_exec", "fft2d_exec_pass", 
            "fft2d_exec_pass_ablated",
            "fft2d_exec_batched",
            "fft2d_backward", "fft2d_destroy", "fft2d_status_string", "fft2d_last_error", "fft2d_plan_describe",
-           "fft2d_plan_twiddles", "fft2d_exec_noalloc", "fft2d_probe_dft16", "fft2d_version")
+           "fft2d_plan_twiddles", "fft2d_exec_noalloc", "fft2d_probe_dft16", "fft2d_probe_tile_copy", "fft2d_probe_lds",
+           "fft2d_version")
 
 
 class Fft2dError(RuntimeError):
@@ -80,13 +81,15 @@ def _load():
     lib.fft2d_plan_twiddles.argtypes = [vp, ci, vp, i64, ctypes.POINTER(i64)]
     lib.fft2d_exec_noalloc.argtypes = [i64, i64, i64, vp, vp, ci, vp]
     lib.fft2d_probe_dft16.argtypes = [ci, vp, vp, i64, ci, vp, vp, vp]
+    lib.fft2d_probe_tile_copy.argtypes = [vp, vp, i64, i64, ci, ci, ci, vp, vp, vp]
+    lib.fft2d_probe_lds.argtypes = [ci, ci, vp, i64, ctypes.POINTER(i64), vp, vp, vp]
     lib.fft2d_version.argtypes = []
     lib.fft2d_version.restype = ci
     for f in ("fft2d_plan", "fft2d_plan_batched", "fft2d_exec", "fft2d_exec_pass", "fft2d_exec_pass_timed",
               "fft2d_exec_pass_ablated",
               "fft2d_exec_batched", "fft2d_backward",
               "fft2d_destroy", "fft2d_plan_describe", "fft2d_plan_twiddles", "fft2d_exec_noalloc",
-              "fft2d_probe_dft16"):
+              "fft2d_probe_dft16", "fft2d_probe_tile_copy", "fft2d_probe_lds"):
         getattr(lib, f).restype = ci
     return lib
 
@@ -198,6 +201,23 @@ def fft2d_probe_dft16(method: int, in_ptr: int, out_ptr: int, count: int, reps: 
     """count 16-point vectors, (Pi F / 4)^reps applied in registers by butterflies or MFMA (rate probe)."""
     _check(lib.fft2d_probe_dft16(int(method), in_ptr, out_ptr, int(count), int(reps), start_event or None,
                                  stop_event or None, stream), "fft2d_probe_dft16")
+
+
+def fft2d_probe_tile_copy(in_ptr: int, out_ptr: int, rows: int, cols: int, tile_cols: int, residues: int,
+                          nontemporal: bool, start_event: int = 0, stop_event: int = 0, stream: int = 0) -> None:
+    """Copy of a rows x cols grid in column tiles of tile_cols columns (access-pattern probe)."""
+    _check(lib.fft2d_probe_tile_copy(in_ptr, out_ptr, int(rows), int(cols), int(tile_cols), int(residues),
+                                     1 if nontemporal else 0, start_event or None, stop_event or None, stream),
+           "fft2d_probe_tile_copy")
+
+
+def fft2d_probe_lds(width_bytes: int, write: bool, sink_ptr: int, sink_floats: int, start_event: int = 0,
+                    stop_event: int = 0, stream: int = 0) -> int:
+    """LDS read or write bandwidth probe; returns the bytes the launch moves."""
+    b = ctypes.c_int64(0)
+    _check(lib.fft2d_probe_lds(int(width_bytes), 1 if write else 0, sink_ptr, int(sink_floats), ctypes.byref(b),
+                               start_event or None, stop_event or None, stream), "fft2d_probe_lds")
+    return int(b.value)
 
 
 def fft2d_destroy(plan: int) -> None:

@@ -18,7 +18,7 @@ CSRC = os.path.join(PKG, "csrc")
 OBJDIR = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libfft2d.so")
 SOURCES = ["fft_kernels_row.hip", "fft_kernels_col.hip", "fft_kernels_split.hip", "fft_kernels_grid.hip",
-           "fft_kernels.hip", "fft_batched.hip", "fft_mfma_probe.hip", "fft2d.cpp"]
+           "fft_kernels.hip", "fft_batched.hip", "fft_mfma_probe.hip", "fft_probes.hip", "fft2d.cpp"]
 ARCH = "gfx950"
 
 # Packed FP32 instructions are kept out of the generated code on purpose.
