@@ -91,7 +91,7 @@ using BC64 = Cfg<64, 8, 64, 1, true, 8, 8>;
 using BC128 = Cfg<128, 16, 64, 1, true, 16, 8>;
 using BC256 = Cfg<256, 16, 32, 1, true, 16, 16>;
 using BC512 = Cfg<512, 16, 16, 1, true, 16, 16, 2>;
-using BC1024 = Cfg<1024, 32, 16, 2, true, 16, 16, 4>;
+using BC1024 = Cfg<1024, 32, 16, 2, true, 32, 32>;
 using BC2048 = Cfg<2048, 32, 8, 2, true, 16, 16, 8>;
 using BC4096 = Cfg<4096, 32, 4, 2, true, 16, 16, 16>;
 using BC8192 = Cfg<8192, 32, 2, 2, true, 16, 16, 32>;
@@ -99,10 +99,13 @@ using BC16384 = Cfg<16384, 32, 1, 2, true, 16, 16, 16, 4>;
 // Row-with-combine configurations of split transforms (512 threads each): M1
 // rows of length L per tile, M1 = C.
 using BRC512 = Cfg<512, 16, 16, 1, false, 16, 16, 2>;
-using BRC1024 = Cfg<1024, 32, 16, 2, false, 16, 16, 4>;
-using BRC2048 = Cfg<2048, 32, 8, 2, false, 16, 16, 8>;
-using BRC4096 = Cfg<4096, 32, 4, 2, false, 16, 16, 16>;
-using BRC8192 = Cfg<8192, 32, 2, 2, false, 16, 16, 32>;
+// The last stage of the row FFT runs across the M1 rows (rowx_tile): its
+// radix times M1 is the points per thread, and the combine needs no exchange
+// of its own.
+using BRC1024 = Cfg<1024, 32, 16, 2, false, 32, 16, 2>;
+using BRC2048 = Cfg<2048, 32, 8, 2, false, 32, 16, 4>;
+using BRC4096 = Cfg<4096, 32, 4, 2, false, 32, 16, 8>;
+using BRC8192 = Cfg<8192, 32, 2, 2, false, 32, 16, 16>;
 
 // Variant-1 configurations (512 threads each): the other points-per-thread
 // count, hence the other tile size (4096 / 8192 / 16384 points) and, for
@@ -241,7 +244,7 @@ __device__ __noinline__ __attribute__((flatten)) void tile(const float2* in, flo
 
 // Tiles t0 .. t0 + cnt - 1 (tile = m2 index) of the row pass with combine of a
 // split transform: in -> work, conjugating the input for the inverse.
-template <class K>
+template <class K, bool XROW>
 __device__ __noinline__ __attribute__((flatten)) void ctile(const float2* in, float2* work, const float2* tw,
                                                             int tw_count, const float2* twc, int rows, int cols,
                                                             int t0, int cnt, int flags, float2* lds) {
@@ -266,7 +269,8 @@ __device__ __noinline__ __attribute__((flatten)) void ctile(const float2* in, fl
   cnt = uniform(cnt);
   for (int i = 0; i < cnt; ++i) {
     if (i > 0) __syncthreads();  // the previous tile's LDS reads are done
-    rowc_tile<K, -1, kAuxNontemporal>(pa, t0 + i, lds, io);
+    if constexpr (XROW) rowx_tile<K, -1, kAuxNontemporal>(pa, t0 + i, lds, io);
+    else rowc_tile<K, -1, kAuxNontemporal>(pa, t0 + i, lds, io);
   }
 }
 
@@ -274,11 +278,11 @@ __device__ __forceinline__ void run_ctile(int cfg, const float2* in, float2* wor
                                           const float2* twc, int rows, int cols, int t0, int cnt, int flags,
                                           float2* lds) {
   switch (cfg) {
-    case 41: ctile<BRC512>(in, work, tw, tw_count, twc, rows, cols, t0, cnt, flags, lds); break;
-    case 42: ctile<BRC1024>(in, work, tw, tw_count, twc, rows, cols, t0, cnt, flags, lds); break;
-    case 43: ctile<BRC2048>(in, work, tw, tw_count, twc, rows, cols, t0, cnt, flags, lds); break;
-    case 44: ctile<BRC4096>(in, work, tw, tw_count, twc, rows, cols, t0, cnt, flags, lds); break;
-    case 45: ctile<BRC8192>(in, work, tw, tw_count, twc, rows, cols, t0, cnt, flags, lds); break;
+    case 41: ctile<BRC512, false>(in, work, tw, tw_count, twc, rows, cols, t0, cnt, flags, lds); break;
+    case 42: ctile<BRC1024, true>(in, work, tw, tw_count, twc, rows, cols, t0, cnt, flags, lds); break;
+    case 43: ctile<BRC2048, true>(in, work, tw, tw_count, twc, rows, cols, t0, cnt, flags, lds); break;
+    case 44: ctile<BRC4096, true>(in, work, tw, tw_count, twc, rows, cols, t0, cnt, flags, lds); break;
+    case 45: ctile<BRC8192, true>(in, work, tw, tw_count, twc, rows, cols, t0, cnt, flags, lds); break;
     default: break;
   }
 }
