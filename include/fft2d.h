@@ -123,9 +123,11 @@ fft2d_status fft2d_plan(fft2d_plan_t* out, int64_t batch, int64_t rows, int64_t 
  * (rows[i] x cols[i], powers of two in [1, 16384]), executed by
  * fft2d_exec_batched in one persistent kernel launch replayed from a HIP graph.
  * rows and cols are host arrays of `count` entries (1 <= count <= 2^24), read
- * during the call only. Radix schedule and tile shape are fixed per length;
- * the persistent grid size, the item order and the work-group granularity come
- * from the library's autotuner, cached per shape set in a text file
+ * during the call only. The persistent grid size, the item order, the
+ * work-group granularity and, for every row and column length of 32 points or
+ * more, one of two radix schedules / tile shapes come from the library's
+ * autotuner (FFT2D_BATCH_VARIANT=0|1 fixes the latter), cached per shape set in
+ * a text file
  * (FFT2D_TUNE=off|cached|full, FFT2D_TUNE_CACHE=<path>, default
  * $HOME/.cache/fft2d_tune.txt). Tuning runs the kernel on two temporary device
  * buffers of the plan's total size, freed before the call returns; if they

@@ -41,3 +41,47 @@ def test_random_shapes_match_oracle(F, a, b, batch, seed):
     z = plan(y, F.INVERSE)
     check(host(y), oracle.fft2_forward(x), "property %s seed %d fwd" % (shape, seed))
     check(host(z), x, "property %s seed %d round trip" % (shape, seed))
+
+
+# Split column transforms on random shapes: N = 1024 ... 8192 columns, the
+# row count a multiple of the split factor M1 the plan would choose for N,
+# both row passes with combine (last stage across rows, separate combine
+# exchange), forced through FFT2D_SPLIT / FFT2D_COMBINE at sizes the oracle
+# handles quickly.
+_M1 = {1024: 16, 2048: 8, 4096: 4, 8192: 4}
+
+
+@settings(max_examples=20, deadline=None, derandomize=True)
+@given(b=st.integers(10, 13), k=st.integers(1, 5), batch=st.integers(1, 2), cross_row=st.booleans(),
+       seed=st.integers(0, 2**31 - 1))
+def test_random_split_shapes_match_oracle(F, b, k, batch, cross_row, seed):
+    import os
+    cols = 1 << b
+    m1 = _M1[cols]
+    rows = m1 << k
+    while rows * cols * batch > (1 << 21) and rows > 2 * m1:
+        rows //= 2
+    shape = (batch, rows, cols)
+    saved = {v: os.environ.get(v) for v in ("FFT2D_SPLIT", "FFT2D_COMBINE")}
+    os.environ["FFT2D_SPLIT"] = str(m1)
+    os.environ["FFT2D_COMBINE"] = "xrow" if cross_row else "classic"
+    try:
+        plan = F.Plan(batch, rows, cols)
+    finally:
+        for v, old in saved.items():
+            if old is None:
+                os.environ.pop(v, None)
+            else:
+                os.environ[v] = old
+    try:
+        desc = plan.describe()
+        assert ("split=%d " % m1) in desc, desc
+        assert ("combine xrow" in desc) == cross_row, desc
+        x = synth.complex_grid(seed, shape)
+        xd = dev(x)
+        y = plan(xd, F.FORWARD)
+        z = plan(y, F.INVERSE)
+        check(host(y), oracle.fft2_forward(x), "split property %s seed %d fwd" % (shape, seed))
+        check(host(z), x, "split property %s seed %d round trip" % (shape, seed))
+    finally:
+        plan.close()
