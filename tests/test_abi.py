@@ -158,3 +158,24 @@ def test_dft16_probe_rejects_bad_arguments_before_touching_the_gpu(L):
         assert f(1, 16, 1 << 40, count, reps, None, None, None) == 2, (count, reps)
     assert f(1, 12, 1 << 40, 64, 8, None, None, None) == 4
     assert f(1, 16, 24, 64, 8, None, None, None) == 9
+
+
+def test_pattern_probes_reject_bad_arguments_before_touching_the_gpu(L):
+    """fft2d_probe_tile_copy validates pointers, tile width, shape, alignment
+    and overlap, and fft2d_probe_lds its width and pointers, on the host."""
+    f = L.lib.fft2d_probe_tile_copy
+    big = 1 << 40
+    assert f(None, big, 2048, 64, 16, 1, 0, None, None, None) == 1
+    assert f(16, big, 2048, 64, 16, 1, 0, 16, None, None) == 1
+    for rows, cols, tc, res in ((2048, 64, 8, 1), (1000, 64, 16, 1), (2048, 64, 16, 0), (2048, 60, 16, 1),
+                                (4096, 64, 16, 3), (1 << 15, 1 << 14, 16, 1)):
+        assert f(16, big, rows, cols, tc, res, 0, None, None, None) == 2, (rows, cols, tc, res)
+    assert f(12, big, 2048, 64, 16, 1, 0, None, None, None) == 4
+    assert f(16, 24, 2048, 64, 16, 1, 0, None, None, None) == 9
+    import ctypes
+    g = L.lib.fft2d_probe_lds
+    n = ctypes.c_int64(0)
+    assert g(8, 0, None, 1 << 20, ctypes.byref(n), None, None, None) == 1
+    assert g(8, 0, 16, 1 << 20, None, None, None, None) == 1
+    assert g(12, 0, 16, 1 << 20, ctypes.byref(n), None, None, None) == 2
+    assert g(8, 1, 16, 1 << 20, ctypes.byref(n), 16, None, None) == 1
