@@ -98,7 +98,9 @@ typedef struct fft2d_plan_s* fft2d_plan_t;
  * (narrow | auto | wide) the column kernel's points per thread (32 | 64; auto
  * takes 64 where there is such a kernel). The split row pass runs the last
  * stage of its row FFT across its M1 rows, so that the M1-point combine needs
- * no LDS exchange of its own (FFT2D_COMBINE=xrow | classic), and column
+ * no LDS exchange of its own (FFT2D_COMBINE=xrow | classic; for 4096-point
+ * rows and at most 1024 tiles with 64 points per thread, FFT2D_COMBINE_WIDE=
+ * auto | on | off), and column
  * passes of 1024 and 2048 points use two radix stages (32 x 32, 64 x 32:
  * FFT2D_COLUMN_STAGES=two | classic), with nontemporal loads for grids of at
  * least 256 MiB (FFT2D_COLUMN_NT=auto | on | off). Grids of 32 x 32,

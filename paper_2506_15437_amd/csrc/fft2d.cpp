@@ -160,6 +160,19 @@ bool use_nontemporal_columns(int64_t points) {
   return points * 8 >= (int64_t(256) << 20);
 }
 
+// Whether a split plan's row pass takes the combine kernel with 64 points per
+// thread (256 threads) where there is one (4096-point rows, M1 = 4) rather
+// than 32 (512 threads): for at most 1024 tiles (one 4096^2 grid), where both
+// run in two rounds of workgroups. Measured on MI355X, row pass, forward, 1 GiB
+// read before each transform: 4096^2 51.6-52.5 against 55.2-55.9 us; two
+// 4096^2 grids 104.2 against 99.5 us. FFT2D_COMBINE_WIDE=auto|on|off overrides.
+bool use_wide_combine(int64_t tiles) {
+  const char* env = std::getenv("FFT2D_COMBINE_WIDE");
+  if (env && std::strcmp(env, "on") == 0) return true;
+  if (env && std::strcmp(env, "off") == 0) return false;
+  return tiles <= 1024;
+}
+
 // Whether a split plan's row pass runs the combine kernel whose last FFT stage
 // works across the workgroup's rows (rowx_kernel: one LDS exchange fewer)
 // rather than the one with a separate combine exchange (rowc_kernel), where
@@ -474,7 +487,7 @@ fft2d_status select_kernels(fft2d_plan_s* p, int64_t batch, int64_t rows, int64_
   p->m2 = rows / p->m1;
 
   if (p->m1 > 1) {
-    p->row_k = find_combine_kernel((int)cols, (int)p->m1, use_cross_row_combine());
+    p->row_k = find_combine_kernel((int)cols, (int)p->m1, use_cross_row_combine(), use_wide_combine(batch * p->m2));
     p->col_k = find_split_column_kernel((int)p->m2, use_wide_columns(), use_two_stage_columns(),
                                         use_nontemporal_columns(batch * rows * cols));
     if (!p->col_k) p->col_k = find_pass_kernel((int)p->m2, true);

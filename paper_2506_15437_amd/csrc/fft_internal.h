@@ -85,8 +85,9 @@ const PassKernel* find_pass_kernel(int L, bool colmode);
 const PassKernel* find_few_tiles_kernel(int L, bool colmode, bool shuffle = false);
 // Row pass with an M1-point combine across M1 rows of length L (nullptr if
 // none); `cross_row` prefers the variant whose last stage runs across the rows
-// (rowx_kernel) where both exist.
-const PassKernel* find_combine_kernel(int L, int m1, bool cross_row = true);
+// (rowx_kernel) where both exist, `wide` one with more than 32 points per
+// thread among those.
+const PassKernel* find_combine_kernel(int L, int m1, bool cross_row = true, bool wide = false);
 // Column pass for the length-M2 columns of a split transform; `two_stage`
 // prefers a two-stage radix schedule (one LDS exchange) where there is one
 // (`nt`: its variant with nontemporal input loads), then `wide` the

@@ -38,16 +38,20 @@ const PassKernel* find_few_tiles_kernel(int L, bool colmode, bool shuffle) {
   return any;
 }
 
-const PassKernel* find_combine_kernel(int L, int m1, bool cross_row) {
+const PassKernel* find_combine_kernel(int L, int m1, bool cross_row, bool wide) {
   int n = 0;
   const PassKernel* tab = combine_kernel_table(&n);
   const PassKernel* any = nullptr;
+  const PassKernel* kind = nullptr;
   for (int i = 0; i < n; ++i) {
     if (tab[i].L != L || tab[i].C != m1) continue;
-    if ((tab[i].xrow != 0) == cross_row) return &tab[i];
+    if ((tab[i].xrow != 0) == cross_row) {
+      if ((tab[i].E > 32) == wide) return &tab[i];
+      if (!kind) kind = &tab[i];
+    }
     if (!any) any = &tab[i];
   }
-  return any;
+  return kind ? kind : any;
 }
 
 const PassKernel* find_split_column_kernel(int L, bool wide, bool two_stage, bool nt) {

@@ -35,6 +35,9 @@ using RX16384x2 = Cfg<16384, 32, 2, 2, false, 32, 32, 16>;
 using RX4096x4 = Cfg<4096, 32, 4, 2, false, 32, 16, 8>;
 using RX2048x8 = Cfg<2048, 32, 8, 2, false, 32, 16, 4>;
 using RX1024x16 = Cfg<1024, 32, 16, 2, false, 32, 16, 2>;
+// 64 points per thread (256 threads, 64 loads in flight per thread) for grids
+// with few tiles.
+using RX4096x4W = Cfg<4096, 64, 4, 2, false, 64, 4, 16>;
 
 const PassKernel kCombineKernels[] = {
     describe<RC8192x2, kKindCombine, 4>(), describe<RC8192x4, kKindCombine, 1, true, true>(),
@@ -44,7 +47,7 @@ const PassKernel kCombineKernels[] = {
     describe<RC1024x16, kKindCombine, 4>(),
     describe<RX8192x4, kKindCrossRow, 1, true, true>(), describe<RX16384x2, kKindCrossRow, 1>(),
     describe<RX4096x4, kKindCrossRow, 4, true, true>(), describe<RX2048x8, kKindCrossRow, 4, true, true>(),
-    describe<RX1024x16, kKindCrossRow, 4>(),
+    describe<RX1024x16, kKindCrossRow, 4>(), describe<RX4096x4W, kKindCrossRow, 1, true, true>(),
 };
 const PassKernel kSplitColKernels[] = {
     describe<S512>(), describe<S1024, kKindPass, 1, false, true>(), describe<S2048>(), describe<S4096>(),

@@ -223,22 +223,26 @@ SPLIT_CASES = [(1, (32, 1024), 16), (2, (64, 1024), 16), (1, (256, 2048), 8), (3
                (1, (8192, 2048), 8), (1, (64, 16384), 2), (2, (32, 16384), 2)]
 
 
-@pytest.mark.parametrize("combine", ["xrow", "classic"])
+@pytest.mark.parametrize("combine", ["xrow", "xrow-narrow", "classic"])
 @pytest.mark.parametrize("batch,shape,m1", SPLIT_CASES, ids=lambda v: str(v))
 def test_split_transform(F, batch, shape, m1, combine, monkeypatch):
     """Forward, inverse, adjoint and in-place split transforms against the
-    oracle, with both row passes with combine: the last FFT stage across the
-    workgroup's rows (xrow, the default where it exists) and the separate
-    combine exchange (classic)."""
+    oracle, with every row pass with combine: the last FFT stage across the
+    workgroup's rows (xrow, the default where it exists; with few tiles and
+    4096-point rows its 64-points-per-thread form, xrow-narrow forcing the
+    32-point one) and the separate combine exchange (classic)."""
     say("case split batch %d shape %dx%d m1 %d %s" % ((batch,) + shape + (m1, combine)))
     monkeypatch.setenv("FFT2D_SPLIT", str(m1))
-    monkeypatch.setenv("FFT2D_COMBINE", combine)
+    monkeypatch.setenv("FFT2D_COMBINE", combine.split("-")[0])
+    monkeypatch.setenv("FFT2D_COMBINE_WIDE", "off" if combine == "xrow-narrow" else "auto")
     plan = F.Plan(batch, *shape)
     try:
         desc = plan.describe()
         assert ("split=%d " % m1) in desc, desc
         if combine == "classic":
             assert " combine]" in desc, desc
+        if combine == "xrow-narrow":
+            assert " E=64 " not in desc.split("col[")[0], desc
         x = synth.complex_grid(m1 + batch, (batch,) + shape)
         xd = dev(x)
         y = host(plan(xd, F.FORWARD))
