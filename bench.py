@@ -663,7 +663,8 @@ def energy(F, torch, rows, cols, seconds):
 
 
 def time_backward(F, torch, batch, rows, cols, steps, warmup, seed):
-    """fft2d_backward (adjoint kernels) against fft2d_exec on the same plan and data."""
+    """fft2d_backward (adjoint kernels) against fft2d_exec on the same plan and
+    data, and one whole differentiation step of sum |W * FFT2(x)|^2."""
     import synth
     x = torch.from_numpy(synth.complex_grid(seed, (batch, rows, cols))).to("cuda")
     out = torch.empty_like(x)
@@ -687,8 +688,23 @@ def time_backward(F, torch, batch, rows, cols, steps, warmup, seed):
     fwd = run(lambda: F.fft2d_exec(plan.handle, x.data_ptr(), out.data_ptr(), F.FORWARD, sh))
     bwd = run(lambda: F.fft2d_backward(plan.handle, x.data_ptr(), out.data_ptr(), F.FORWARD, sh))
     fl = flops_2d(rows, cols, batch)
+    # One differentiation step of the loss sum |W * FFT2(x)|^2 (W real [rows][cols], uniform [0, 1) from seed
+    # seed + 100, broadcast over the batch): the library's forward and adjoint kernels plus torch's elementwise
+    # ops and reduction, as a training step would run them.
+    w = torch.from_numpy(synth.real_weights(seed + 100, (rows, cols))).to("cuda")
+    xg = x.clone().requires_grad_(True)
+
+    def train_step():
+        xg.grad = None
+        y = F.fft2_diff(xg, F.FORWARD)
+        loss = (w * w * (y.real * y.real + y.imag * y.imag)).sum()
+        loss.backward()
+
+    step = run(train_step)
     return {"workload": "batch %d of %dx%d complex64" % (batch, rows, cols), "plain_ms": fwd, "backward_ms": bwd,
-            "backward_over_plain": bwd / fwd, "plain_gflops": fl / fwd / 1e6, "backward_gflops": fl / bwd / 1e6}
+            "backward_over_plain": bwd / fwd, "plain_gflops": fl / fwd / 1e6, "backward_gflops": fl / bwd / 1e6,
+            "loss_step_ms": step, "loss_step": "fft2_diff forward, loss = sum |W * FFT2(x)|^2 (torch), backward",
+            "fft_share_of_loss_step": (fwd + bwd) / step}
 
 
 def _batched_plan(F, shapes, tune, cache):
