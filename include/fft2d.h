@@ -141,7 +141,9 @@ fft2d_status fft2d_plan(fft2d_plan_t* out, int64_t batch, int64_t rows, int64_t 
  * runs columns of rows/M1 points (FFT2D_BATCH_SPLIT=off disables this).
  * Grids of 64x64, 64x128, 128x64, 128x128, 64x256 and 256x64 are transformed
  * whole by one workgroup, with one read and one write of their data
- * (FFT2D_BATCH_GRID=off disables this).
+ * (FFT2D_BATCH_GRID=off disables this). FFT2D_BATCH_GUIDED=1 groups the work
+ * in large units first and small ones at the end of each queue (fewer tile
+ * calls: less memory traffic, the same time on the 512-shape set).
  */
 fft2d_status fft2d_plan_batched(fft2d_plan_t* out, int64_t count, const int64_t* rows, const int64_t* cols);
 

@@ -1,8 +1,10 @@
 // CPU check of the batched path's work schedule (paper_2506_15437_amd/csrc/
-// fft_schedule.hpp), built with g++ and run by tests/test_host.py.
+// fft_schedule.hpp, and its guided regrouping in fft_batched_guided.hpp),
+// built with g++ and run by tests/test_host.py.
 //
-// For many random shape sets and every queue count, item order and group size
-// the library uses, it checks the properties the persistent kernel relies on:
+// For many random shape sets and every queue count, item order, group size and
+// worker count (0: fixed groups) the library uses, it checks the properties
+// the persistent kernel relies on:
 //   * every row tile, column tile, whole-grid item and copy item of every
 //     transform appears exactly once;
 //   * all items of a transform sit in one queue, and there every row item of
@@ -13,6 +15,7 @@
 //   * every item holds 1 ... 65535 tiles.
 // Prints "ok <cases>" and exits 0, or prints the first violation and exits 1.
 #include "../../paper_2506_15437_amd/csrc/fft_schedule.hpp"
+#include "../../paper_2506_15437_amd/csrc/fft_batched_guided.hpp"
 
 #include <cstdio>
 #include <cstdlib>
@@ -28,8 +31,17 @@ int fail(const char* what, long a, long b) {
   return 1;
 }
 
-int check(const std::vector<Shape>& f, int nq, int order, int gk) {
-  const Schedule sc = build_schedule(f, nq, order, gk);
+int check(const std::vector<Shape>& f, int nq, int order, int gk, int workers) {
+  const Schedule fixed = build_schedule(f, nq, order, gk);
+  const Schedule sc = workers > 0 ? guided(fixed, f, nq, workers, (int64_t)gk * 1024 / 8) : fixed;
+  if (workers > 0) {
+    // regrouping keeps the order of the tiles within each queue and never makes more groups or items
+    if (sc.groups.size() > fixed.groups.size()) return fail("guided groups", (long)sc.groups.size(), 0);
+    if (sc.items.size() > fixed.items.size()) return fail("guided items", (long)sc.items.size(), 0);
+    for (int x = 0; x <= kMaxQueues; ++x)
+      if ((sc.qbeg[x] == sc.qbeg[kMaxQueues]) != (fixed.qbeg[x] == fixed.qbeg[kMaxQueues]))
+        return fail("guided queue emptiness", x, sc.qbeg[x]);
+  }
   const int ng = (int)sc.groups.size() - 1;
   const int ni = (int)sc.items.size();
   if (ng < 0) return fail("no group end", ng, 0);
@@ -131,13 +143,15 @@ int main(int argc, char** argv) {
     if (n == 0) f.assign(3, Shape{});  // three 1 x 1 transforms
     for (int nq = 1; nq <= 9; ++nq)
       for (int order = 0; order < 2; ++order)
-        for (int gk : {64, 256, 1024}) {
-          if (check(f, nq, order, gk)) {
-            std::printf("set %d count %d nq %d order %d group_kib %d\n", n, count, nq, order, gk);
-            return 1;
+        for (int gk : {64, 256, 1024})
+          for (int workers : {0, 1, 32, 96}) {
+            if (check(f, nq, order, gk, workers)) {
+              std::printf("set %d count %d nq %d order %d group_kib %d workers %d\n", n, count, nq, order, gk,
+                          workers);
+              return 1;
+            }
+            ++cases;
           }
-          ++cases;
-        }
   }
   std::printf("ok %ld\n", cases);
   return 0;

@@ -56,18 +56,22 @@ def _run(F, plan, xs, direction, outs=None):
     return ins, res
 
 
-@pytest.mark.parametrize("tune,sync", [("off", "auto"), ("full", "auto"), ("off", "fenced")])
-def test_batched_mixed_shapes(F, tune, sync, monkeypatch):
+@pytest.mark.parametrize("tune,sync,guided", [("off", "auto", "0"), ("full", "auto", "0"), ("off", "fenced", "0"),
+                                               ("off", "auto", "1"), ("full", "auto", "1")])
+def test_batched_mixed_shapes(F, tune, sync, guided, monkeypatch):
     """Forward and inverse of every length 1 .. 16384 as rows and as columns;
-    sync "fenced" forces the single-queue path with agent-scope release / acquire."""
+    sync "fenced" forces the single-queue path with agent-scope release / acquire;
+    guided "1" groups the work in large units first (merged tile runs)."""
     monkeypatch.setenv("FFT2D_TUNE", tune)
     monkeypatch.setenv("FFT2D_BATCH_SYNC", sync)
-    say("case batched mixed shapes tune=%s sync=%s" % (tune, sync))
+    monkeypatch.setenv("FFT2D_BATCH_GUIDED", guided)
+    say("case batched mixed shapes tune=%s sync=%s guided=%s" % (tune, sync, guided))
     xs = synth.batched_grids(11, MIXED)
     plan = F.BatchedPlan(MIXED)
     try:
         say(plan.describe())
         assert ("fenced" in plan.describe()) == (sync == "fenced")
+        assert (" guided " in plan.describe()) == (guided == "1")
         _, ys = _run(F, plan, xs, F.FORWARD)
         _, zs = _run(F, plan, xs, F.INVERSE)
         wf, wi = Worst("batched mixed fwd"), Worst("batched mixed inv")
@@ -87,14 +91,16 @@ SPLIT_SHAPES = [(2048, 512), (2048, 1024), (2048, 2048), (2048, 4096), (2048, 81
 SPLIT_EXPECTED = 8  # the first eight are split
 
 
-@pytest.mark.parametrize("split", ["auto", "off"])
-def test_batched_split_transforms(F, split, monkeypatch):
+@pytest.mark.parametrize("split,guided", [("auto", "0"), ("off", "0"), ("auto", "1")])
+def test_batched_split_transforms(F, split, guided, monkeypatch):
     """Forward, inverse, in place and half in place for tall grids in one plan,
-    split (row pass with an M1-point combine, columns of M / M1) or not."""
+    split (row pass with an M1-point combine, columns of M / M1) or not, with
+    fixed or guided work groups."""
     import torch
     monkeypatch.setenv("FFT2D_TUNE", "off")
     monkeypatch.setenv("FFT2D_BATCH_SPLIT", split)
-    say("case batched split=%s" % split)
+    monkeypatch.setenv("FFT2D_BATCH_GUIDED", guided)
+    say("case batched split=%s guided=%s" % (split, guided))
     xs = synth.batched_grids(14, SPLIT_SHAPES)
     plan = F.BatchedPlan(SPLIT_SHAPES)
     try:
