@@ -91,6 +91,8 @@ def kernel_role(name):
 # expected (kind, direction) of each pass of the profiled sequences
 ROUND_TRIP_ROLES = {"fwd_row": ("row", -1), "fwd_col": ("col", -1), "inv_row": ("row", 1), "inv_col": ("col", 1)}
 FORWARD_ROLES = {"fwd_row": ("row", -1), "fwd_col": ("col", -1)}
+# fft2d_backward with the forward direction runs the opposite-sign kernels
+BACKWARD_ROLES = {"bwd_row": ("row", 1), "bwd_col": ("col", 1)}
 
 
 def _assign_passes(rows, roles):
@@ -189,7 +191,7 @@ def summarize_stats(stats_dir, timed=0):
             trace = list(csv.DictReader(fh))
         by_name = {}
         for r in trace:
-            if kernel_role(r["Kernel_Name"]) is not None:
+            if kernel_role(r["Kernel_Name"]) is not None or "::batched_kernel(" in r["Kernel_Name"]:
                 by_name.setdefault(r["Kernel_Name"], []).append(r)
         for name, rs in by_name.items():
             rs.sort(key=lambda r: int(r["Dispatch_Id"]))
@@ -722,6 +724,122 @@ def _batched_plan(F, shapes, tune, cache):
                 os.environ[k] = v
 
 
+BATCHED_SEED = 4  # the 512-shape workload of the default run
+ONLY_EXTRA = ("backward-8x2048x2048", "batched-512")
+
+
+def only_batched(F, torch, steps, warmup):
+    """The 512-shape batched workload alone, for rocprofv3: the tuned plan (its
+    tuning trials launch the batched kernel too), `warmup` graph replays, then
+    `steps` replays each bracketed by events; the timed replays are the
+    kernel's last `steps` dispatches. Prints one JSON line."""
+    import tempfile
+
+    import synth
+    shapes = synth.pow2_shapes(BATCHED_SEED, 512)
+    xs = [torch.from_numpy(x).to("cuda") for x in synth.batched_grids(BATCHED_SEED, shapes)]
+    ys = [torch.empty_like(x) for x in xs]
+    with tempfile.TemporaryDirectory() as tmp:
+        plan = _batched_plan(F, shapes, "full", os.path.join(tmp, "tune.txt"))
+    stream = torch.cuda.current_stream()
+    sh = int(stream.cuda_stream)
+    iarr = F.pointer_array([x.data_ptr() for x in xs])
+    oarr = F.pointer_array([y.data_ptr() for y in ys])
+    for _ in range(warmup):
+        plan.exec_ptrs(iarr, oarr, F.FORWARD, sh)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for a, b in ev:
+        a.record(stream)
+        plan.exec_ptrs(iarr, oarr, F.FORWARD, sh)
+        b.record(stream)
+    torch.cuda.synchronize()
+    ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    points = sum(r * c for r, c in shapes)
+    print(json.dumps({"only": "batched-512", "steps": steps, "warmup": warmup, "protocol": "graph replays back to back",
+                      "ms_per_replay": round(ms, 5), "points": points,
+                      "gbps_at_32_bytes_per_point": round(32.0 * points / (ms * 1e-3) / 1e9, 1),
+                      "frac": _frac(32.0 * points, ms), "plan": plan.describe()}), flush=True)
+    plan.close()
+
+
+def only_backward(F, torch, steps, warmup):
+    """fft2d_backward (forward-direction adjoint) of a batch of 8 grids of
+    2048 x 2048 alone, for rocprofv3, under the protocol of only_config: every
+    call preceded by a 1 GiB read; prints one JSON line."""
+    import synth
+    x = torch.from_numpy(synth.complex_grid(5, (8, 2048, 2048))).to("cuda")
+    y = torch.empty_like(x)
+    scratch = torch.empty(SCRATCH_FLOATS, dtype=torch.float32, device="cuda")
+    plan = F.get_plan(8, 2048, 2048, x.device)
+    stream = torch.cuda.current_stream()
+    sh = int(stream.cuda_stream)
+    for _ in range(warmup):
+        scratch.sum()
+        F.fft2d_backward(plan.handle, x.data_ptr(), y.data_ptr(), F.FORWARD, sh)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for a, b in ev:
+        scratch.sum()
+        a.record(stream)
+        F.fft2d_backward(plan.handle, x.data_ptr(), y.data_ptr(), F.FORWARD, sh)
+        b.record(stream)
+    torch.cuda.synchronize()
+    ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    nbytes = 2 * BYTES_PER_POINT_PER_PASS * 8 * 2048 * 2048
+    print(json.dumps({"only": "backward-8x2048x2048", "steps": steps, "warmup": warmup,
+                      "protocol": "1 GiB read before each call", "ms_per_call": round(ms, 5),
+                      "frac": _frac(nbytes, ms), "plan": plan.describe()}), flush=True)
+
+
+def summarize_batched_traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, timed,
+                              copy_bytes=4096 * 4096 * 8):
+    """HBM bytes per launch of the batched kernel from rocprofv3 FETCH_SIZE /
+    WRITE_SIZE runs of `bench.py --only batched-512`, over its last `timed`
+    dispatches (the timed graph replays), scaled as in summarize_traffic."""
+    import synth
+    factors = {}
+    for name, d in (("FETCH_SIZE", copy_fetch_dir), ("WRITE_SIZE", copy_write_dir)):
+        vals = [float(r["Counter_Value"]) for r in _counter_rows(d)
+                if "copyBuffer" in r["Kernel_Name"] and r["Counter_Name"] == name]
+        factors[name] = (copy_bytes / 1024.0) / float(np.median(vals))
+    kib = {}
+    kernel = None
+    for name, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        rows = [r for r in _counter_rows(d) if r["Counter_Name"] == name and "batched_kernel" in r["Kernel_Name"]]
+        if len(rows) < timed:
+            raise ValueError("%d batched_kernel dispatches in %s, fewer than %d" % (len(rows), d, timed))
+        rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+        kib[name] = float(np.mean([float(r["Counter_Value"]) for r in rows[-timed:]]))
+        kernel = rows[-1]["Kernel_Name"]
+    points = sum(r * c for r, c in synth.pow2_shapes(BATCHED_SEED, 512))
+    rd = kib["FETCH_SIZE"] * 1024 * factors["FETCH_SIZE"]
+    wr = kib["WRITE_SIZE"] * 1024 * factors["WRITE_SIZE"]
+    return "\n".join([
+        "source_hash = %s" % kernel_source_hash(),
+        "fetch_factor = %.4f" % factors["FETCH_SIZE"],
+        "write_factor = %.4f" % factors["WRITE_SIZE"],
+        "points = %d" % points,
+        "algorithmic_bytes_at_32_per_point = %d" % (32 * points),
+        "launch bytes %d read %d write %d fetch_kib %.1f write_kib %.1f dispatches %d kernel %s"
+        % (rd + wr, rd, wr, kib["FETCH_SIZE"], kib["WRITE_SIZE"], timed, kernel)])
+
+
+def summarize_batched_counters(run_dir, timed):
+    """Mean of every counter of a rocprofv3 --pmc run of `bench.py --only
+    batched-512` over the batched kernel's last `timed` dispatches."""
+    rows = [r for r in _counter_rows(run_dir) if "batched_kernel" in r["Kernel_Name"]]
+    by = {}
+    for r in rows:
+        by.setdefault(r["Counter_Name"], []).append(r)
+    lines = ["source_hash = %s" % kernel_source_hash()]
+    for name in sorted(by):
+        rs = sorted(by[name], key=lambda r: int(r["Dispatch_Id"]))[-timed:]
+        lines.append("%s %.6g (mean of %d dispatches)" % (name, float(np.mean([float(r["Counter_Value"]) for r in rs])),
+                                                          len(rs)))
+    return "\n".join(lines)
+
+
 def time_batched(F, torch, steps, warmup, seed):
     """512 transforms of 2^a x 2^b (a, b in [6, 11] from `seed`): one graph
     replay of the persistent kernel, with the autotuner's choice (grid size,
@@ -912,27 +1030,41 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the backward and batched comparisons")
     ap.add_argument("--copy-only", action="store_true",
                     help="only run plain device copies of the 4096x4096 grid (calibrates rocprofv3 byte counters)")
-    ap.add_argument("--only", choices=sorted(ONLY),
+    ap.add_argument("--only", choices=sorted(ONLY) + list(ONLY_EXTRA),
                     help="run only this configuration's forward transform (warmup + steps back to back, then "
-                         "steps pass by pass with bound events) and print its per-pass times")
+                         "steps pass by pass with bound events) and print its per-pass times; "
+                         "backward-8x2048x2048: fft2d_backward calls; batched-512: replays of the batched plan")
     ap.add_argument("--vendor-context", action="store_true",
                     help="also time torch.fft.fft2 (ROCm's FFT library) on the large configurations, for context")
     ap.add_argument("--summarize-traffic", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
                     help="print HBM bytes per pass from four rocprofv3 --pmc output folders, then exit")
+    ap.add_argument("--summarize-batched-traffic", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
+                    help="print HBM bytes per launch of the batched kernel (its last --timed dispatches) from four "
+                         "rocprofv3 --pmc output folders of --only batched-512 and --copy-only, then exit")
+    ap.add_argument("--summarize-batched-counters", metavar="DIR",
+                    help="print the mean of every counter over the batched kernel's last --timed dispatches from a "
+                         "rocprofv3 --pmc output folder of --only batched-512, then exit")
     ap.add_argument("--summarize-counters", nargs="+", metavar="DIR",
                     help="print the mean of every counter per pass from rocprofv3 --pmc output folders, then exit")
     ap.add_argument("--summarize-stats", metavar="DIR",
                     help="print the kernel rows of a rocprofv3 --kernel-trace --stats output folder, then exit")
     ap.add_argument("--timed", type=int, default=0,
                     help="for --summarize-stats: also average each pass kernel's last TIMED dispatches")
-    ap.add_argument("--profiled", default="roundtrip", choices=["roundtrip"] + sorted(ONLY),
-                    help="for --summarize-*: the workload profiled: the 4096x4096 round trip (default) or the "
-                         "forward transform of an --only configuration")
+    ap.add_argument("--profiled", default="roundtrip", choices=["roundtrip", "backward-8x2048x2048"] + sorted(ONLY),
+                    help="for --summarize-*: the workload profiled: the 4096x4096 round trip (default), "
+                         "fft2d_backward at 8x2048x2048, or the forward transform of an --only configuration")
     args = ap.parse_args()
-    roles = ROUND_TRIP_ROLES if args.profiled == "roundtrip" else FORWARD_ROLES
+    roles = {"roundtrip": ROUND_TRIP_ROLES, "backward-8x2048x2048": BACKWARD_ROLES}.get(args.profiled, FORWARD_ROLES)
     if args.summarize_traffic:
-        b, r_, c_, _ = ONLY["4096x4096" if args.profiled == "roundtrip" else args.profiled]
+        b, r_, c_, _ = ONLY[{"roundtrip": "4096x4096", "backward-8x2048x2048": "8x2048x2048"}.get(args.profiled,
+                                                                                                   args.profiled)]
         print(summarize_traffic(*args.summarize_traffic, points=b * r_ * c_, roles=roles))
+        return
+    if args.summarize_batched_counters:
+        print(summarize_batched_counters(args.summarize_batched_counters, args.timed or 1))
+        return
+    if args.summarize_batched_traffic:
+        print(summarize_batched_traffic(*args.summarize_batched_traffic, timed=args.timed or 1))
         return
     if args.summarize_counters:
         print(summarize_counters(*args.summarize_counters, roles=roles))
@@ -962,6 +1094,12 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
         print(json.dumps({"copy_only": True, "bytes_per_copy": 2 * x.numel() * 8, "copies": args.warmup + args.steps}))
+        return
+    if args.only == "batched-512":
+        only_batched(F, torch, args.steps, args.warmup)
+        return
+    if args.only == "backward-8x2048x2048":
+        only_backward(F, torch, args.steps, args.warmup)
         return
     if args.only:
         only_config(F, torch, args.only, args.steps, args.warmup)
@@ -1033,7 +1171,7 @@ def main():
         log("bench: energy per transform (1024 x 1024 and 4096 x 4096)")
         result["energy"] = [energy(F, torch, 1024, 1024, 1.5), energy(F, torch, 4096, 4096, 1.5)]
         log("bench: batched 512 shapes vs 512 plain launches")
-        result["batched_vs_plain"] = time_batched(F, torch, 10, 3, 4)
+        result["batched_vs_plain"] = time_batched(F, torch, 10, 3, BATCHED_SEED)
         if args.vendor_context:
             log("bench: torch.fft.fft2 (vendor FFT) on the same inputs, context")
             result["vendor_fft_context"] = vendor_fft_context(F, torch)

@@ -224,3 +224,29 @@ def test_tune_cache_parsing(tmp_path):
                    timeout=120)
     r = subprocess.run([exe, str(tmp_path)], capture_output=True, text=True, timeout=60)
     assert r.returncode == 0 and r.stdout.strip() == "ok", r.stdout + r.stderr
+
+
+def test_batched_traffic_summary_uses_the_timed_dispatches(tmp_path):
+    """The batched kernel's bytes per launch are the scaled mean over its last
+    `timed` dispatches (tuning trials come first in a run and are left out);
+    other kernels are ignored, and too few dispatches are an error."""
+    import bench
+    grid = 4096 * 4096 * 8
+    kib = grid / 1024
+    name = "fft2d::(anonymous namespace)::batched_kernel(fft2d::(anonymous namespace)::BatchArgs)"
+    fetch = [[d, name, "FETCH_SIZE", 999.0] for d in range(1, 4)]  # tuning trials
+    fetch += [[d, name, "FETCH_SIZE", 3000.0 + d] for d in (10, 11)]
+    fetch += [[5, "some_other_kernel", "FETCH_SIZE", 1.0e9]]
+    write = [[d, name, "WRITE_SIZE", 500.0] for d in range(1, 4)] + [[d, name, "WRITE_SIZE", 4000.0] for d in (10, 11)]
+    _write_counters(tmp_path / "f", fetch)
+    _write_counters(tmp_path / "w", write)
+    _write_counters(tmp_path / "cf", [[1, "__amd_rocclr_copyBuffer", "FETCH_SIZE", kib / 2]])
+    _write_counters(tmp_path / "cw", [[1, "__amd_rocclr_copyBuffer", "WRITE_SIZE", kib]])
+    args = [str(tmp_path / d) for d in ("f", "w", "cf", "cw")]
+    text = bench.summarize_batched_traffic(*args, timed=2)
+    launch = [l.split() for l in text.splitlines() if l.startswith("launch ")][0]
+    assert int(launch[4]) == round(3010.5 * 1024 * 2) and int(launch[6]) == round(4000.0 * 1024)
+    assert int(launch[2]) == int(launch[4]) + int(launch[6])
+    assert "fetch_factor = 2.0000" in text and "dispatches 2" in text
+    with pytest.raises(ValueError):
+        bench.summarize_batched_traffic(*args, timed=6)
