@@ -650,7 +650,7 @@ std::vector<sched::Shape> sched_shapes(const BatchedPlan& bp) {
 }
 
 // Guided grouping (fft_batched_guided.hpp) with FFT2D_BATCH_GUIDED=1. On the
-// 512-shape set it cuts the kernel's memory traffic from 1.17 to 1.07 times
+// 512-shape set it cuts the kernel's memory traffic from 1.17 to 1.05-1.07 times
 // the algorithmic bytes (fewer calls, fewer register saves) but not its time,
 // so fixed groups stay the default.
 bool use_guided_groups() {
