@@ -144,6 +144,9 @@ fft2d_status fft2d_plan(fft2d_plan_t* out, int64_t batch, int64_t rows, int64_t 
  * (FFT2D_BATCH_GRID=off disables this). FFT2D_BATCH_GUIDED=1 groups the work
  * in large units first and small ones at the end of each queue (fewer tile
  * calls: less memory traffic, the same time on the 512-shape set).
+ * Every transform runs on one XCD, so a batch of a few large grids of one
+ * shape is faster as a uniform plan (fft2d_plan with a batch count), whose
+ * passes spread each grid over the whole GPU.
  */
 fft2d_status fft2d_plan_batched(fft2d_plan_t* out, int64_t count, const int64_t* rows, const int64_t* cols);
 
