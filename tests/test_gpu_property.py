@@ -85,3 +85,43 @@ def test_random_split_shapes_match_oracle(F, b, k, batch, cross_row, seed):
         check(host(z), x, "split property %s seed %d round trip" % (shape, seed))
     finally:
         plan.close()
+
+
+# Batched plans of random shape sets (2^a x 2^b, a, b in [0, 11], at most 2^21
+# points per set), with fixed or guided work groups and the untuned schedule:
+# every transform forward and inverse against the oracle.
+@settings(max_examples=12, deadline=None, derandomize=True)
+@given(dims=st.lists(st.tuples(st.integers(0, 11), st.integers(0, 11)), min_size=1, max_size=12),
+       guided=st.booleans(), seed=st.integers(0, 2**31 - 1))
+def test_random_batched_sets_match_oracle(F, dims, guided, seed):
+    import os
+    shapes = []
+    total = 0
+    for a, b in dims:
+        if total + (1 << (a + b)) > (1 << 21):
+            continue
+        shapes.append((1 << a, 1 << b))
+        total += 1 << (a + b)
+    if not shapes:
+        shapes = [(1, 1)]
+    saved = {v: os.environ.get(v) for v in ("FFT2D_TUNE", "FFT2D_BATCH_GUIDED")}
+    os.environ["FFT2D_TUNE"] = "off"
+    os.environ["FFT2D_BATCH_GUIDED"] = "1" if guided else "0"
+    try:
+        plan = F.BatchedPlan(shapes)
+    finally:
+        for v, old in saved.items():
+            if old is None:
+                os.environ.pop(v, None)
+            else:
+                os.environ[v] = old
+    try:
+        assert (" guided " in plan.describe()) == guided, plan.describe()
+        xs = synth.batched_grids(seed % 1000, shapes)
+        ys = plan([dev(x) for x in xs], F.FORWARD)
+        zs = plan([dev(x) for x in xs], F.INVERSE)
+        for x, y, z, s in zip(xs, ys, zs, shapes):
+            check(host(y), oracle.fft2_forward(x), "batched property %s guided %d fwd" % (s, guided))
+            check(host(z), oracle.ifft2(x), "batched property %s guided %d inv" % (s, guided))
+    finally:
+        plan.close()
