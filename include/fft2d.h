@@ -144,9 +144,13 @@ fft2d_status fft2d_plan(fft2d_plan_t* out, int64_t batch, int64_t rows, int64_t 
  * (FFT2D_BATCH_GRID=off disables this). FFT2D_BATCH_GUIDED=1 groups the work
  * in large units first and small ones at the end of each queue (fewer tile
  * calls: less memory traffic, the same time on the 512-shape set).
- * Every transform runs on one XCD, so a batch of a few large grids of one
- * shape is faster as a uniform plan (fft2d_plan with a batch count), whose
- * passes spread each grid over the whole GPU.
+ * In the persistent kernel every transform runs on one XCD; a grid of at
+ * least 2^22 points that holds at least 1/16 of the plan's points (1/(2 nq),
+ * nq the number of XCD queues) runs instead as a plain transform: the row and
+ * column kernels of a uniform plan the batched plan owns, launched on the same
+ * stream after the persistent kernel (FFT2D_BATCH_PLAIN=off disables this).
+ * A batch of many grids of one shape is still fastest as a uniform plan
+ * (fft2d_plan with a batch count: two launches for the whole batch).
  */
 fft2d_status fft2d_plan_batched(fft2d_plan_t* out, int64_t count, const int64_t* rows, const int64_t* cols);
 

@@ -577,6 +577,10 @@ struct BatchedPlan {
   std::vector<int32_t> m1;          // split factor per transform (1 = plain)
   std::vector<uint8_t> grid;        // 1: one whole-grid item
   int n_grid = 0;
+  std::vector<uint8_t> plain;       // 1: run by a uniform plan's row and column kernels (see plain_transform)
+  int n_plain = 0;
+  std::vector<fft2d_plan_t> sub;    // per transform: its uniform plan (plain transforms), else null
+  std::vector<fft2d_plan_t> sub_owned;  // one uniform plan per distinct shape of the plain transforms
   std::vector<int64_t> work_off;    // split transforms: offset in d_work (points)
   int64_t work_points = 0;
   int n_split = 0;
@@ -658,12 +662,21 @@ bool use_guided_groups() {
   return env && (std::string(env) == "1" || std::string(env) == "on");
 }
 
-// The schedule for a launch of mult workgroups per CU.
+// The schedule for a launch of mult workgroups per CU, over the transforms the
+// persistent kernel runs (plain transforms have no items).
 sched::Schedule build_schedule(const BatchedPlan& bp, int order, int group_kib, int mult) {
-  const std::vector<sched::Shape> shapes = sched_shapes(bp);
+  const std::vector<sched::Shape> all = sched_shapes(bp);
+  std::vector<sched::Shape> shapes;
+  std::vector<uint32_t> ids;
+  for (int64_t i = 0; i < bp.count; ++i) {
+    if (bp.plain[(size_t)i]) continue;
+    shapes.push_back(all[(size_t)i]);
+    ids.push_back((uint32_t)i);
+  }
   sched::Schedule sc = sched::build_schedule(shapes, bp.nq, order, group_kib);
   if (bp.guided)
     sc = sched::guided(sc, shapes, bp.nq, mult * bp.num_cu / std::max(1, bp.nq), (int64_t)group_kib * 1024 / 8);
+  for (sched::Item& it : sc.items) it.x = ids[it.x >> 2] << 2 | (it.x & 3u);
   return sc;
 }
 
@@ -780,7 +793,7 @@ std::vector<std::pair<int, int>> tunable_lengths(const BatchedPlan& bp) {
   bool used[2][tune::kVariantSlots] = {};
   for (int64_t i = 0; i < bp.count; ++i) {
     const size_t k = (size_t)i;
-    if (bp.grid[k]) continue;
+    if (bp.grid[k] || bp.plain[k]) continue;
     const int N = bp.cols[k], M = bp.rows[k], m1 = bp.m1[k];
     if (m1 == 1 && N > 1) used[0][ilog2i(N)] = true;
     if (M > 1) used[1][ilog2i(M / m1)] = true;
@@ -811,6 +824,20 @@ float time_candidate(BatchedPlan* bp, int mult, int order, int group_kib, hipStr
 }
 
 }  // namespace
+
+// A transform holding at least 1 / (2 nq) of the plan's points and at least
+// 2^22 points runs as a plain transform: its uniform plan's row and column
+// kernels, launched on the caller's stream after the persistent kernel, spread
+// it over every XCD. In the persistent kernel a transform runs on one XCD, so
+// a plan of a few large grids leaves XCDs idle or gives each XCD one long row
+// phase and one long column phase with a barrier between them: 4 x 1024 x 8192
+// takes 0.46 ms there and 0.23 ms as plain transforms, 8 x 2048^2 0.31 against
+// 0.27 ms. Smaller grids stay in the persistent kernel, where two launches per
+// grid would cost more than they gain (16 x 2048 x 512: 0.15 ms against 0.28).
+// FFT2D_BATCH_PLAIN=off keeps every transform in the persistent kernel.
+static bool plain_transform(int64_t points, int64_t total, int nq) {
+  return points >= (int64_t(1) << 22) && points * 2 * nq >= total;
+}
 
 fft2d_status create_batched(int64_t count, const int64_t* rows, const int64_t* cols, BatchedPlan** out,
                             std::string* err) {
@@ -907,6 +934,44 @@ fft2d_status create_batched(int64_t count, const int64_t* rows, const int64_t* c
       bp->fenced = 1;
     }
   }
+  // Plain transforms (see plain_transform); the work buffer, split and
+  // whole-grid counts then cover the persistent kernel's transforms only.
+  {
+    const char* plain_env = std::getenv("FFT2D_BATCH_PLAIN");
+    const bool allow_plain = !(plain_env && std::string(plain_env) == "off");
+    bp->plain.assign((size_t)count, 0);
+    bp->sub.assign((size_t)count, nullptr);
+    std::map<std::pair<int, int>, fft2d_plan_t> by_shape;
+    bp->work_points = 0;
+    bp->n_split = 0;
+    bp->n_grid = 0;
+    for (int64_t i = 0; i < count; ++i) {
+      const size_t k = (size_t)i;
+      const int64_t pts = (int64_t)bp->rows[k] * bp->cols[k];
+      bp->work_off[k] = 0;
+      if (allow_plain && plain_transform(pts, bp->total_points, bp->nq)) {
+        bp->plain[k] = 1;
+        ++bp->n_plain;
+        bp->grid[k] = 0;
+        auto it = by_shape.find({bp->rows[k], bp->cols[k]});
+        if (it == by_shape.end()) {
+          fft2d_plan_t sp = nullptr;
+          const fft2d_status st = fft2d_plan(&sp, 1, bp->rows[k], bp->cols[k]);
+          if (st != FFT2D_OK) return fail(st, std::string("uniform plan of a large transform: ") + fft2d_last_error());
+          bp->sub_owned.push_back(sp);
+          it = by_shape.emplace(std::make_pair(bp->rows[k], bp->cols[k]), sp).first;
+        }
+        bp->sub[k] = it->second;
+        continue;
+      }
+      if (bp->m1[k] > 1) {
+        bp->work_off[k] = bp->work_points;
+        bp->work_points += pts;
+        ++bp->n_split;
+      }
+      bp->n_grid += bp->grid[k];
+    }
+  }
   // twiddle tables of every configuration (all, so a pointer change never needs new tables)
   {
     std::vector<float2> host;
@@ -993,14 +1058,15 @@ fft2d_status create_batched(int64_t count, const int64_t* rows, const int64_t* c
   assign_configs(bp);
   std::ostringstream keys;
   bp->guided = use_guided_groups();
-  keys << "gfx950|v5|" << (bp->guided ? "guided|" : "") << (bp->n_split ? "split|" : "")
+  keys << "gfx950|v5|" << (bp->guided ? "guided|" : "") << (bp->n_plain ? "plain" + std::to_string(bp->n_plain) + "|" : "")
+       << (bp->n_split ? "split|" : "")
        << (bp->n_grid ? "whole|" : "")
        << (forced_variant >= 0 ? "variant" + std::to_string(forced_variant) + "|" : "") << shape_signature(*bp);
   char keyhex[32];
   std::snprintf(keyhex, sizeof(keyhex), "%016llx", (unsigned long long)fnv1a(keys.str()));
   bool have = false;
   tune::Choice cached;
-  if (mode == "off") {
+  if (mode == "off" || bp->n_plain == count) {
     have = true;
     bp->tune_source = "default";
   } else if (mode != "full" && tune::lookup(cache_path(), keyhex, &cached)) {
@@ -1149,10 +1215,20 @@ fft2d_status exec_batched(BatchedPlan* bp, const void* const* in, void* const* o
     bp->last_in.assign(in, in + bp->count);
     bp->last_out.assign(out, out + bp->count);
   }
-  e = hipGraphLaunch(bp->exec[direction == FFT2D_INVERSE ? 1 : 0], s);
-  if (e != hipSuccess) {
-    *err = std::string("graph launch: ") + hipGetErrorName(e);
-    return FFT2D_ERR_HIP;
+  if (bp->n_items > 0) {
+    e = hipGraphLaunch(bp->exec[direction == FFT2D_INVERSE ? 1 : 0], s);
+    if (e != hipSuccess) {
+      *err = std::string("graph launch: ") + hipGetErrorName(e);
+      return FFT2D_ERR_HIP;
+    }
+  }
+  for (int64_t i = 0; i < bp->count; ++i) {
+    if (!bp->plain[(size_t)i]) continue;
+    const fft2d_status st = fft2d_exec(bp->sub[(size_t)i], in[i], out[i], direction, (void*)s);
+    if (st != FFT2D_OK) {
+      *err = std::string("plain transform ") + std::to_string(i) + ": " + fft2d_last_error();
+      return st;
+    }
   }
   return FFT2D_OK;
 }
@@ -1176,13 +1252,15 @@ void destroy_batched(BatchedPlan* bp) {
   if (bp->d_work) (void)hipFree(bp->d_work);
   if (bp->h_err) (void)hipHostFree(bp->h_err);
   if (bp->d_tw) (void)hipFree(bp->d_tw);
+  for (fft2d_plan_t sp : bp->sub_owned) (void)fft2d_destroy(sp);
   delete bp;
 }
 
 std::string describe_batched(const BatchedPlan* bp) {
   std::ostringstream os;
   os << "batched count=" << bp->count << " points=" << bp->total_points << " items=" << bp->n_items
-     << " groups=" << bp->n_groups << " group_kib=" << bp->group_kib << " split=" << bp->n_split
+     << " groups=" << bp->n_groups << " group_kib=" << bp->group_kib << " plain=" << bp->n_plain
+     << " split=" << bp->n_split
      << " whole=" << bp->n_grid
      << " queues=" << bp->nq
      << (bp->fenced ? " fenced" : " xcd-local") << " grid=" << bp->grid_mult << "x" << bp->num_cu

@@ -27,6 +27,9 @@ def F():
 @pytest.fixture(autouse=True)
 def _tune_cache(tmp_path, monkeypatch):
     monkeypatch.setenv("FFT2D_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    # every transform in the persistent kernel unless a test says otherwise (large grids of a
+    # plan would otherwise run as plain transforms and bypass the kernel paths under test)
+    monkeypatch.setenv("FFT2D_BATCH_PLAIN", "off")
 
 
 # every length 1 ... 2048 appears as rows and as cols, plus degenerate 1 x 1
@@ -401,3 +404,63 @@ def test_batched_tuner_choice_is_cached(F, monkeypatch, tmp_path):
     for x, y, s in zip(xs, ya, shapes):
         w.add(host(y), oracle.fft2_forward(host(x)), s)
     w.report()
+
+
+@pytest.mark.parametrize("shapes,expected", [
+    ([(2048, 2048), (64, 64), (2048, 2048), (256, 128), (1024, 4096), (1024, 256), (2048, 2048)], 4),
+    ([(2048, 2048), (2048, 2048)], 2),
+], ids=["mixed", "all-plain"])
+def test_batched_plain_transforms(F, shapes, expected, monkeypatch):
+    """Grids that hold a large share of a plan's points run as plain transforms
+    (a uniform plan's kernels over the whole GPU) beside the persistent kernel:
+    forward, inverse, in place, half in place and a pointer change, against the
+    oracle and against the same plan with FFT2D_BATCH_PLAIN=off."""
+    import torch
+    monkeypatch.setenv("FFT2D_TUNE", "off")
+    monkeypatch.delenv("FFT2D_BATCH_PLAIN")
+    say("case batched plain transforms %s" % (shapes,))
+    xs = synth.batched_grids(21, shapes)
+    plan = F.BatchedPlan(shapes)
+    try:
+        desc = plan.describe()
+        say(desc)
+        import re
+        nq = int(re.search(r" queues=(\d+) ", desc).group(1))
+        total = sum(r * c for r, c in shapes)
+        rule = sum(1 for r, c in shapes if r * c >= (1 << 22) and r * c * 2 * nq >= total)
+        assert (" plain=%d " % rule) in desc, desc
+        if nq == 8:
+            assert rule == expected, (rule, expected)
+        if rule == len(shapes):
+            assert " items=0 " in desc, desc
+        ins, ys = _run(F, plan, xs, F.FORWARD)
+        _, zs = _run(F, plan, xs, F.INVERSE)
+        wf, wi = Worst("batched plain fwd"), Worst("batched plain inv")
+        for x, y, z, s in zip(xs, ys, zs, shapes):
+            wf.add(host(y), oracle.fft2_forward(x), s)
+            wi.add(host(z), oracle.ifft2(x), s)
+        wf.report()
+        wi.report()
+        inplace = [t.clone() for t in ins]
+        plan(inplace, F.FORWARD, inplace)
+        torch.cuda.synchronize()
+        for u, v in zip(ys, inplace):
+            assert torch.equal(u, v)
+        mixed_in = [t.clone() for t in ins]
+        mixed_out = [t if k % 2 == 0 else torch.empty_like(t) for k, t in enumerate(mixed_in)]
+        plan(mixed_in, F.FORWARD, mixed_out)
+        torch.cuda.synchronize()
+        for u, v in zip(ys, mixed_out):
+            assert torch.equal(u, v)
+    finally:
+        plan.close()
+    monkeypatch.setenv("FFT2D_BATCH_PLAIN", "off")
+    ref_plan = F.BatchedPlan(shapes)
+    try:
+        assert " plain=0 " in ref_plan.describe()
+        _, rs = _run(F, ref_plan, xs, F.FORWARD)
+        for y, r, s in zip(ys, rs, shapes):
+            rel, mx = errors_dev(y, r)
+            assert rel <= TOL and mx <= TOL, (s, rel, mx)
+    finally:
+        ref_plan.close()
