@@ -149,8 +149,9 @@ fft2d_status fft2d_plan(fft2d_plan_t* out, int64_t batch, int64_t rows, int64_t 
  * nq the number of XCD queues) runs instead as a plain transform: the row and
  * column kernels of a uniform plan the batched plan owns, launched on the same
  * stream after the persistent kernel (FFT2D_BATCH_PLAIN=off disables this).
- * A batch of many grids of one shape is still fastest as a uniform plan
- * (fft2d_plan with a batch count: two launches for the whole batch).
+ * Plain transforms of one shape whose inputs, and outputs, follow each other
+ * in memory in index order (slices of one tensor) run as one uniform batch:
+ * two launches for all of them, as fft2d_plan with a batch count would.
  */
 fft2d_status fft2d_plan_batched(fft2d_plan_t* out, int64_t count, const int64_t* rows, const int64_t* cols);
 

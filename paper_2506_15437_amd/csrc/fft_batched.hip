@@ -581,6 +581,14 @@ struct BatchedPlan {
   int n_plain = 0;
   std::vector<fft2d_plan_t> sub;    // per transform: its uniform plan (plain transforms), else null
   std::vector<fft2d_plan_t> sub_owned;  // one uniform plan per distinct shape of the plain transforms
+  // Plain transforms of one shape, in index order, and a uniform plan of all of
+  // them as one batch: used when their buffers are consecutive in memory.
+  struct PlainGroup {
+    int rows = 0, cols = 0;
+    std::vector<int64_t> idx;
+    fft2d_plan_t whole = nullptr;
+  };
+  std::vector<PlainGroup> plain_groups;
   std::vector<int64_t> work_off;    // split transforms: offset in d_work (points)
   int64_t work_points = 0;
   int n_split = 0;
@@ -962,6 +970,17 @@ fft2d_status create_batched(int64_t count, const int64_t* rows, const int64_t* c
           it = by_shape.emplace(std::make_pair(bp->rows[k], bp->cols[k]), sp).first;
         }
         bp->sub[k] = it->second;
+        auto same_shape = [&](const BatchedPlan::PlainGroup& pg) {
+          return pg.rows == bp->rows[k] && pg.cols == bp->cols[k];
+        };
+        auto g = std::find_if(bp->plain_groups.begin(), bp->plain_groups.end(), same_shape);
+        if (g == bp->plain_groups.end()) {
+          bp->plain_groups.emplace_back();
+          g = bp->plain_groups.end() - 1;
+          g->rows = bp->rows[k];
+          g->cols = bp->cols[k];
+        }
+        g->idx.push_back(i);
         continue;
       }
       if (bp->m1[k] > 1) {
@@ -970,6 +989,11 @@ fft2d_status create_batched(int64_t count, const int64_t* rows, const int64_t* c
         ++bp->n_split;
       }
       bp->n_grid += bp->grid[k];
+    }
+    for (BatchedPlan::PlainGroup& g : bp->plain_groups) {
+      if (g.idx.size() < 2) continue;
+      const fft2d_status st = fft2d_plan(&g.whole, (int64_t)g.idx.size(), g.rows, g.cols);
+      if (st != FFT2D_OK) return fail(st, std::string("uniform plan of large transforms: ") + fft2d_last_error());
     }
   }
   // twiddle tables of every configuration (all, so a pointer change never needs new tables)
@@ -1222,12 +1246,33 @@ fft2d_status exec_batched(BatchedPlan* bp, const void* const* in, void* const* o
       return FFT2D_ERR_HIP;
     }
   }
-  for (int64_t i = 0; i < bp->count; ++i) {
-    if (!bp->plain[(size_t)i]) continue;
-    const fft2d_status st = fft2d_exec(bp->sub[(size_t)i], in[i], out[i], direction, (void*)s);
-    if (st != FFT2D_OK) {
-      *err = std::string("plain transform ") + std::to_string(i) + ": " + fft2d_last_error();
-      return st;
+  // Plain transforms: a group whose inputs follow each other in memory, and
+  // whose outputs too (the same buffers, or buffers apart from the inputs),
+  // runs as one batch (two launches); otherwise each grid on its own.
+  for (const BatchedPlan::PlainGroup& g : bp->plain_groups) {
+    const uintptr_t bytes = (uintptr_t)g.rows * g.cols * 8;
+    const uintptr_t in0 = reinterpret_cast<uintptr_t>(in[g.idx[0]]);
+    const uintptr_t out0 = reinterpret_cast<uintptr_t>(out[g.idx[0]]);
+    bool run = g.whole != nullptr;
+    for (size_t j = 1; run && j < g.idx.size(); ++j)
+      run = reinterpret_cast<uintptr_t>(in[g.idx[j]]) == in0 + j * bytes &&
+            reinterpret_cast<uintptr_t>(out[g.idx[j]]) == out0 + j * bytes;
+    const uintptr_t span = bytes * g.idx.size();
+    if (run && in0 != out0 && in0 < out0 + span && out0 < in0 + span) run = false;
+    if (run) {
+      const fft2d_status st = fft2d_exec(g.whole, in[g.idx[0]], out[g.idx[0]], direction, (void*)s);
+      if (st != FFT2D_OK) {
+        *err = std::string("plain transforms from ") + std::to_string(g.idx[0]) + ": " + fft2d_last_error();
+        return st;
+      }
+      continue;
+    }
+    for (int64_t i : g.idx) {
+      const fft2d_status st = fft2d_exec(bp->sub[(size_t)i], in[i], out[i], direction, (void*)s);
+      if (st != FFT2D_OK) {
+        *err = std::string("plain transform ") + std::to_string(i) + ": " + fft2d_last_error();
+        return st;
+      }
     }
   }
   return FFT2D_OK;
@@ -1253,6 +1298,8 @@ void destroy_batched(BatchedPlan* bp) {
   if (bp->h_err) (void)hipHostFree(bp->h_err);
   if (bp->d_tw) (void)hipFree(bp->d_tw);
   for (fft2d_plan_t sp : bp->sub_owned) (void)fft2d_destroy(sp);
+  for (const BatchedPlan::PlainGroup& g : bp->plain_groups)
+    if (g.whole) (void)fft2d_destroy(g.whole);
   delete bp;
 }
 

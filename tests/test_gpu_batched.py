@@ -464,3 +464,37 @@ def test_batched_plain_transforms(F, shapes, expected, monkeypatch):
             assert rel <= TOL and mx <= TOL, (s, rel, mx)
     finally:
         ref_plan.close()
+
+
+def test_batched_plain_transforms_of_one_tensor(F, monkeypatch):
+    """Plain transforms of one shape whose buffers follow each other (slices of
+    one tensor) run as one uniform batch; out of place, in place, and with the
+    slices given out of order (then grid by grid), all against the oracle."""
+    import torch
+    monkeypatch.setenv("FFT2D_TUNE", "off")
+    monkeypatch.delenv("FFT2D_BATCH_PLAIN")
+    shapes = [(2048, 2048)] * 4
+    say("case batched plain transforms of one tensor")
+    x = synth.complex_grid(22, (4, 2048, 2048))
+    ref = oracle.fft2_forward(x)
+    plan = F.BatchedPlan(shapes)
+    try:
+        assert " plain=4 " in plan.describe(), plan.describe()
+        xd = dev(x)
+        yd = torch.empty_like(xd)
+        plan([xd[k] for k in range(4)], F.FORWARD, [yd[k] for k in range(4)])
+        w = Worst("batched plain, one tensor")
+        for k in range(4):
+            w.add(host(yd[k]), ref[k], shapes[k])
+        zd = xd.clone()
+        plan([zd[k] for k in range(4)], F.FORWARD, [zd[k] for k in range(4)])
+        for k in range(4):
+            w.add(host(zd[k]), ref[k], shapes[k])
+        order = [2, 0, 3, 1]
+        od = torch.empty_like(xd)
+        plan([xd[k] for k in order], F.FORWARD, [od[k] for k in order])
+        for k in range(4):
+            w.add(host(od[k]), ref[k], shapes[k])
+        w.report()
+    finally:
+        plan.close()
