@@ -151,7 +151,10 @@ fft2d_status fft2d_plan(fft2d_plan_t* out, int64_t batch, int64_t rows, int64_t 
  * stream after the persistent kernel (FFT2D_BATCH_PLAIN=off disables this).
  * Plain transforms of one shape whose inputs, and outputs, follow each other
  * in memory in index order (slices of one tensor) run as one uniform batch:
- * two launches for all of them, as fft2d_plan with a batch count would.
+ * two launches for all of them, as fft2d_plan with a batch count would. These
+ * owned uniform plans hold device memory like any uniform plan (a split shape's
+ * work buffer: one grid for the single-grid plan, all grids of the shape for
+ * the batch plan).
  */
 fft2d_status fft2d_plan_batched(fft2d_plan_t* out, int64_t count, const int64_t* rows, const int64_t* cols);
 
